@@ -1,0 +1,203 @@
+/*
+ * lb.h - C ABI of the MI355X (gfx950) two-species multirange lattice
+ * Boltzmann library.
+ *
+ * The method (Benzi, Bernaschi, Sbragaglia & Succi, arXiv:1004.5058, section
+ * "Lattice Boltzmann with multirange interactions"):
+ *   f_is(r + c_i, t + 1) - f_is(r, t) =
+ *       -(1/tau) [ f_is(r, t) - f^eq_is(rho_s, u + tau F_s / rho_s) ]     Eq. (1)
+ *   rho_s = sum_i f_is,  u = sum_s sum_i f_is c_i / sum_s rho_s
+ *   f^eq_i(rho, v) = w_i rho [1 + v.c_i/c_S^2 + (v.c_i)^2/(2 c_S^4) - v.v/(2 c_S^2)]
+ *   F_s = F^a_s + F^r_s + F^X_s                                           Eq. (2)
+ *   F^a_s = -G^a_s psi_s(r) sum_{belt 1}     w_i c_i psi_s(r + c_i)
+ *   F^r_s = -G^r_s psi_s(r) sum_{belts 1-2}  p_i c_i psi_s(r + c_i)
+ *   F^X_s = -(G_AB / rho0) rho_s(r) sum_{belt 1} w_i c_i rho_s'(r + c_i)
+ *   psi(rho) = rho0 (1 - exp(-rho / rho0))
+ * on the D2Q9 lattice (c_S^2 = 1/3) with the 24-offset interaction stencil of
+ * Fig. 1.  Belt 1 uses the D2Q9 weights; belts 1-2 use the isotropic two-belt
+ * weights p = 4/63, 4/135, 1/180, 2/945, 1/15120 for |c|^2 = 1, 2, 4, 5, 8.
+ * G < 0 attracts, G > 0 repels.
+ *
+ * Geometry: x (index fastest) is periodic.  y is either periodic or bounded by
+ * half-way bounce-back walls at y = -1/2 and y = ny - 1/2 moving along x at
+ * u_bot and u_top.  A population leaving through a wall returns to its node
+ * reversed, plus 2 w_i rho_s (c_i . u_wall)/c_S^2 with rho_s the node's
+ * pre-collision density.  psi and rho beyond a wall are the even mirror of the
+ * first two fluid rows.
+ *
+ * D2Q9 direction order used wherever populations cross this ABI:
+ *   0 (0,0)  1 (1,0)  2 (0,1)  3 (-1,0)  4 (0,-1)
+ *   5 (1,1)  6 (-1,1) 7 (-1,-1) 8 (1,-1)
+ *
+ * Conventions
+ *   - Every function returns an lb_status; a negative value is an error and
+ *     lb_last_error() (thread-local) describes it.  No C++ exception crosses
+ *     this boundary.
+ *   - Device memory: the caller allocates the device state (any allocator; a
+ *     torch uint8 tensor works) of the size lb_state_bytes / lbb_state_bytes
+ *     report, keeps it alive until *_destroy, and frees it afterwards.  The
+ *     handle owns only host metadata and HIP graphs; *_destroy never frees the
+ *     caller's memory.  The state must be 256-byte aligned.
+ *   - Streams: all device work is enqueued on the hipStream_t given at init
+ *     (NULL = the legacy default stream).  lb_step / lbb_step only enqueue;
+ *     functions that return host data synchronise that stream.
+ *   - Host arrays of fields are float64, row-major (ny, nx), x fastest.
+ *   - Calls on one handle must not overlap (not thread-safe per handle).
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,      /* invalid argument (bad size, tau <= 1/2, non-finite or rho <= 0 input, ...) */
+    LB_ENOMEM = -2,      /* caller's device state too small, or a host allocation failed */
+    LB_EDEVICE = -3,     /* a HIP runtime call failed (message has the HIP error string) */
+    LB_ENONFINITE = -4,  /* the watchdog found a non-finite or non-positive density */
+    LB_ESTATE = -5       /* call out of order (e.g. load of a checkpoint of another shape) */
+} lb_status;
+
+/* Storage precision of the populations.  Every format stores the deviation
+ * d_is = f_is - w_i rho_ref_s from the rest equilibrium at the reference
+ * densities, rounded to nearest-even, and the step computes on deviations
+ * (density deviations, deviations of psi from psi(rho_ref)), so the rounding
+ * error scales with the departure from the reference state rather than with
+ * f itself.  Arithmetic is FP64 for LB_F64 and FP32 otherwise. */
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3 } lb_storage;
+
+typedef struct {
+    int32_t nx, ny;       /* lattice sites along x (periodic) and y; 1 <= nx, 2 <= ny */
+    int32_t walls_y;      /* 0: periodic in y; 1: moving bounce-back walls */
+    int32_t storage;      /* lb_storage */
+    double tau;           /* BGK relaxation time, > 1/2 (Eq. (1)) */
+    double rho0;          /* psi reference density and F^X normaliser, > 0 */
+    double g_aa1, g_aa2;  /* G^a_AA (belt 1), G^r_AA (belts 1-2) */
+    double g_bb1, g_bb2;  /* G^a_BB, G^r_BB */
+    double g_ab;          /* G^X_AB = G^X_BA (belt 1) */
+    double u_top, u_bot;  /* wall velocities along x (walls_y = 1) */
+    double rho_ref_a, rho_ref_b; /* storage base; <= 0 selects the domain mean of
+                                    the initial density of that species */
+    int32_t profile;      /* 1: accumulate the line-averaged u_x(y) every step */
+    int32_t reserved;
+} lb_params;
+
+typedef struct lb_handle lb_handle;
+
+/* Device bytes a single lattice with these parameters needs. */
+lb_status lb_state_bytes(const lb_params* p, size_t* bytes);
+
+/* Validates p, lays the lattice out in dev_state and sets
+ * f_is(r, 0) = f^eq_i(rho_s(r), u(r)).  rho_a, rho_b: host (ny, nx) float64,
+ * finite and > 0.  ux, uy: host (ny, nx) float64 or NULL for zero.  Blocks
+ * until the initial state is on the device. */
+lb_status lb_init(const lb_params* p, void* dev_state, size_t bytes, void* hip_stream,
+                  const double* rho_a, const double* rho_b, const double* ux, const double* uy,
+                  lb_handle** out);
+
+/* Enqueues n >= 0 time steps of Eq. (1) (collision, forcing, streaming, walls)
+ * and the wall-stress accumulation.  Asynchronous. */
+lb_status lb_step(lb_handle* h, int32_t n);
+
+/* Moments of the current populations, computed in FP64 on the device and
+ * copied to host arrays (any may be NULL): rho_a, rho_b, and u = j / rho.
+ * Synchronises the stream. */
+lb_status lb_fields(lb_handle* h, double* rho_a, double* rho_b, double* ux, double* uy);
+
+/* Same, into caller-provided device arrays (ny*nx float64 each, any may be
+ * NULL).  Asynchronous. */
+lb_status lb_fields_device(lb_handle* h, double* rho_a, double* rho_b, double* ux, double* uy);
+
+/* The current populations decoded to float64, host array of shape
+ * (2, 9, ny, nx) in the direction order above.  Synchronises. */
+lb_status lb_populations(lb_handle* h, double* f);
+
+/* Time-averaged wall shear stress over the steps since init or the last
+ * lb_stress_reset: sigma_bot = <F_bot,x>/nx and sigma_top = -<F_top,x>/nx
+ * with F the x momentum a wall receives per step (both positive when the top
+ * wall moves faster than the bottom one).  nsamples = steps averaged.  The
+ * per-step sums are accumulated in FP64 on the device.  Synchronises. */
+lb_status lb_stress(lb_handle* h, double* sig_bot, double* sig_top, int64_t* nsamples);
+lb_status lb_stress_reset(lb_handle* h);
+
+/* Time average of U_x(y) = (1/nx) sum_x u_x(x, y) over the same window as
+ * lb_stress (requires p->profile = 1).  prof: host array of ny doubles.  The
+ * u_x averaged is the pre-collision barycentric velocity of each step. */
+lb_status lb_profile(lb_handle* h, double* prof, int64_t* nsamples);
+
+/* FP64 domain sums: out[0] = mass A, out[1] = mass B, out[2] = sum j_x,
+ * out[3] = sum j_y, out[4] = number of sites with a non-finite or
+ * non-positive density.  Synchronises; returns LB_ENONFINITE if out[4] > 0. */
+lb_status lb_sums(lb_handle* h, double out[5]);
+
+/* Run the sums every `every` steps inside lb_step (0 = off, the default) and
+ * latch a device flag; lb_fields/lb_stress/lb_sums then report
+ * LB_ENONFINITE. */
+lb_status lb_set_watchdog(lb_handle* h, int32_t every);
+
+/* Launch shape of the step kernel: bx threads per block (64, 128 or 256) =
+ * lattice columns per tile, ly rows per tile (>= 1).  0 keeps the current
+ * choice.  Results are bitwise independent of the shape. */
+lb_status lb_set_launch(lb_handle* h, int32_t bx, int32_t ly);
+
+/* HIP graph use in lb_step: steps per captured graph (0 = launch each step
+ * directly).  Default 32. */
+lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
+
+/* Checkpoint: the populations in their storage format, the step count and
+ * the FP64 stress/profile accumulators.  lb_save with buf = NULL reports the
+ * size in *bytes.  Both synchronise.  lb_load requires a handle of the same
+ * shape and storage (else LB_ESTATE). */
+lb_status lb_save(lb_handle* h, void* buf, size_t* bytes);
+lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
+
+/* Steps taken since init (or restored by lb_load). */
+lb_status lb_time(lb_handle* h, int64_t* t);
+
+/* Releases the handle (not the caller's device memory). */
+lb_status lb_destroy(lb_handle* h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* lb_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched form: n independent lattices of their own sizes and parameters,
+ * advanced together by one persistent step kernel per time step (HIP graph
+ * of many steps).  All lattices share the storage precision of params[0].
+ * Arrays of per-lattice host pointers follow the single-lattice rules.
+ */
+typedef struct lbb_handle lbb_handle;
+
+lb_status lbb_state_bytes(const lb_params* params, int32_t n, size_t* bytes);
+lb_status lbb_init(const lb_params* params, int32_t n, void* dev_state, size_t bytes,
+                   void* hip_stream, const double* const* rho_a, const double* const* rho_b,
+                   const double* const* ux, const double* const* uy, lbb_handle** out);
+lb_status lbb_step(lbb_handle* h, int32_t nsteps);
+/* Per-lattice time-averaged wall stresses (arrays of n) and sample count. */
+lb_status lbb_stress(lbb_handle* h, double* sig_bot, double* sig_top, int64_t* nsamples);
+lb_status lbb_stress_reset(lbb_handle* h);
+/* Lattice k's fields / profile, as lb_fields / lb_profile. */
+lb_status lbb_fields(lbb_handle* h, int32_t k, double* rho_a, double* rho_b, double* ux, double* uy);
+lb_status lbb_profile(lbb_handle* h, int32_t k, double* prof, int64_t* nsamples);
+/* Launch shape (as lb_set_launch) and grid size (0 = one block per tile,
+ * > 0 = persistent grid of that many blocks). */
+lb_status lbb_set_launch(lbb_handle* h, int32_t bx, int32_t ly, int32_t grid);
+lb_status lbb_set_graph(lbb_handle* h, int32_t steps_per_graph);
+lb_status lbb_destroy(lbb_handle* h);
+
+/* Device time of the last `nsteps` steps of one lattice or batch, measured
+ * with HIP events around the step kernels on the handle's stream: average
+ * milliseconds per step-kernel launch.  Enqueues nsteps steps and
+ * synchronises.  Used by the benchmark for the roofline figure. */
+lb_status lb_time_steps(lb_handle* h, int32_t nsteps, double* ms_per_step);
+lb_status lbb_time_steps(lbb_handle* h, int32_t nsteps, double* ms_per_step);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_H */

@@ -1,0 +1,822 @@
+// Host runtime and C ABI (include/lb.h) of the multirange lattice Boltzmann
+// library: parameter validation, the layout of the caller's device state,
+// work decomposition, HIP-graph replay of the step kernel, reductions and
+// checkpoints.  No compute happens on the host; every array operation is a
+// kernel in lb_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "lb_device.hpp"
+#include "lb_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(LB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_size(int storage)
+{
+    switch (storage) {
+    case LB_F64: return 8;
+    case LB_F32: return 4;
+    case LB_F16DEV: return 2;
+    case LB_BF16DEV: return 2;
+    default: return 0;
+    }
+}
+
+// Two-belt weights on |c|^2 = 1, 2, 4, 5, 8 and D2Q9 belt-1 weights.
+const double P12[5] = {4.0 / 63.0, 4.0 / 135.0, 1.0 / 180.0, 2.0 / 945.0, 1.0 / 15120.0};
+const double W1[2] = {1.0 / 9.0, 1.0 / 36.0};
+const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+lb_status validate(const lb_params* p, int storage0)
+{
+    if (!p) return fail(LB_EINVAL, "null parameters");
+    if (p->nx < 1 || p->ny < 2) return fail(LB_EINVAL, "need nx >= 1 and ny >= 2 (got %d x %d)", p->nx, p->ny);
+    if (p->nx > 65536 || p->ny > 65536) return fail(LB_EINVAL, "lattice side above 65536");
+    if (p->storage < 0 || p->storage > 3) return fail(LB_EINVAL, "unknown storage %d", p->storage);
+    if (storage0 >= 0 && p->storage != storage0)
+        return fail(LB_EINVAL, "all lattices of a batch share one storage precision");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LB_EINVAL, "rho0 must be > 0");
+    const double g[] = {p->g_aa1, p->g_aa2, p->g_bb1, p->g_bb2, p->g_ab, p->u_top, p->u_bot,
+                        p->rho_ref_a, p->rho_ref_b};
+    for (double v : g)
+        if (!std::isfinite(v)) return fail(LB_EINVAL, "non-finite coupling, wall speed or reference density");
+    if (p->walls_y != 0 && p->walls_y != 1) return fail(LB_EINVAL, "walls_y must be 0 or 1");
+    // byte offsets inside one species' planes must fit the 32-bit buffer offset
+    const size_t es = storage_size(p->storage);
+    const size_t pitch = align_up((size_t)p->nx, 64);
+    if (9ull * pitch * p->ny * es >= (1ull << 32))
+        return fail(LB_EINVAL, "lattice too large: one species' populations exceed 4 GiB");
+    return LB_OK;
+}
+
+struct Lat {
+    lb_params p;
+    int pitch = 0, ngroups = 0;
+    long long plane = 0;
+    size_t off_f[2] = {0, 0}, off_stress = 0, off_prof = 0, end = 0;
+    double rho_ref[2] = {0, 0};
+};
+
+// Layout: [descs][partials][results] then per lattice [f0][f1][stress][prof].
+struct Layout {
+    size_t off_desc = 0, off_part = 0, off_res = 0, total = 0;
+};
+
+Layout plan(std::vector<Lat>& lats)
+{
+    Layout L;
+    const int n = (int)lats.size();
+    L.off_desc = 0;
+    L.off_part = align_up(sizeof(lbk::LatDesc) * n, ALIGN);
+    L.off_res = L.off_part + align_up(sizeof(double) * 5 * lbk::sums_blocks(), ALIGN);
+    // results: 5 sums + flag slot + 2 per lattice stress + profile staging handled in f buffers
+    size_t off = L.off_res + align_up(sizeof(double) * (8 + 2 * n), ALIGN);
+    for (auto& a : lats) {
+        const size_t es = storage_size(a.p.storage);
+        a.pitch = (int)align_up((size_t)a.p.nx, 64);
+        a.plane = (long long)a.pitch * a.p.ny;
+        a.ngroups = (a.p.nx + 63) / 64;
+        const size_t fbytes = align_up(18ull * a.plane * es, ALIGN);
+        a.off_f[0] = off;
+        a.off_f[1] = off + fbytes;
+        a.off_stress = off + 2 * fbytes;
+        a.off_prof = a.off_stress + align_up(sizeof(double) * 2 * a.p.nx, ALIGN);
+        const size_t pbytes = a.p.profile ? align_up(sizeof(double) * (size_t)a.ngroups * a.p.ny, ALIGN) : 0;
+        a.end = a.off_prof + pbytes;
+        off = a.end;
+    }
+    L.total = off;
+    return L;
+}
+
+void fill_desc(const Lat& a, lbk::LatDesc& d)
+{
+    std::memset(&d, 0, sizeof d);
+    const lb_params& p = a.p;
+    d.off_f[0] = (long long)a.off_f[0];
+    d.off_f[1] = (long long)a.off_f[1];
+    d.off_stress = (long long)a.off_stress;
+    d.off_prof = p.profile ? (long long)a.off_prof : -1;
+    d.plane = a.plane;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.pitch = a.pitch;
+    d.walls = p.walls_y;
+    d.ngroups = a.ngroups;
+    d.tau = p.tau;
+    d.omega = 1.0 / p.tau;
+    d.rho0 = p.rho0;
+    d.inv_rho0 = 1.0 / p.rho0;
+    const double ga[2] = {p.g_aa1, p.g_bb1}, gr[2] = {p.g_aa2, p.g_bb2};
+    for (int s = 0; s < 2; ++s) {
+        d.ks[s][0] = ga[s] * W1[0] + gr[s] * P12[0];
+        d.ks[s][1] = ga[s] * W1[1] + gr[s] * P12[1];
+        for (int k = 2; k < 5; ++k) d.ks[s][k] = gr[s] * P12[k];
+    }
+    d.kx[0] = p.g_ab / p.rho0 * W1[0];
+    d.kx[1] = p.g_ab / p.rho0 * W1[1];
+    d.u_top = p.u_top;
+    d.u_bot = p.u_bot;
+    for (int s = 0; s < 2; ++s) {
+        for (int i = 0; i < 9; ++i) d.wref[9 * s + i] = W9[i] * a.rho_ref[s];
+        d.rref[s] = a.rho_ref[s];
+        d.psiref[s] = -p.rho0 * std::expm1(-a.rho_ref[s] / p.rho0);
+        d.epsi[s] = p.rho0 * std::exp(-a.rho_ref[s] / p.rho0);
+        d.frref[s] = (float)d.rref[s];
+        d.fpsiref[s] = (float)d.psiref[s];
+        d.fepsi[s] = (float)d.epsi[s];
+    }
+    d.ftau = (float)d.tau;
+    d.fomega = (float)d.omega;
+    d.frho0 = (float)d.rho0;
+    d.finv_rho0 = (float)d.inv_rho0;
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < 5; ++k) d.fks[s][k] = (float)d.ks[s][k];
+    d.fkx[0] = (float)d.kx[0];
+    d.fkx[1] = (float)d.kx[1];
+    d.fu_top = (float)d.u_top;
+    d.fu_bot = (float)d.u_bot;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- the batch --
+
+struct lbb_handle {
+    std::vector<Lat> lats;
+    std::vector<lbk::LatDesc> descs;
+    Layout lay;
+    int storage = 1;
+    char* base = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;   // private stream used only to record graphs
+    int cur = 0;                     // buffer holding f(t)
+    int64_t t = 0, nsamples = 0;
+    int bx = 256, ly = 64, grid = 0; // grid 0: one block per tile
+    int ntot = 0;
+    int graph_steps = 32;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};   // graph starting from buffer 0 / 1
+    int watchdog = 0;
+    int flag_host = 0;
+    double* d_part() { return (double*)(base + lay.off_part); }
+    double* d_res() { return (double*)(base + lay.off_res); }
+    int* d_flag() { return (int*)(base + lay.off_res + 6 * sizeof(double)); }
+    lbk::LatDesc* d_desc() { return (lbk::LatDesc*)(base + lay.off_desc); }
+};
+
+struct lb_handle {
+    lbb_handle b;
+};
+
+namespace {
+
+void drop_graphs(lbb_handle* h)
+{
+    for (auto& e : h->exec)
+        if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+}
+
+// Work decomposition for launch shape (bx, ly): tiles per lattice, each
+// lattice's first item rounded up to a multiple of 8 (one tile per XCD slot).
+lb_status decompose(lbb_handle* h)
+{
+    int item = 0;
+    for (size_t k = 0; k < h->lats.size(); ++k) {
+        const Lat& a = h->lats[k];
+        lbk::LatDesc& d = h->descs[k];
+        d.nstrip = (a.p.nx + h->bx - 1) / h->bx;
+        d.ly = std::min(h->ly, a.p.ny);
+        d.nseg = (a.p.ny + d.ly - 1) / d.ly;
+        d.nitems = d.nstrip * d.nseg;
+        item = (item + 7) / 8 * 8;
+        d.item_begin = item;
+        item += d.nitems;
+    }
+    h->ntot = item;
+    HIP_TRY(hipMemcpyAsync(h->d_desc(), h->descs.data(), sizeof(lbk::LatDesc) * h->descs.size(),
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    return LB_OK;
+}
+
+int launch_grid(const lbb_handle* h)
+{
+    if (h->grid > 0) return h->grid;
+    return std::max(1, h->ntot);
+}
+
+lb_status launch_one(lbb_handle* h, hipStream_t s, int src)
+{
+    hipError_t e = lbk::launch_step(h->storage, h->bx, h->base, h->d_desc(), (int)h->lats.size(),
+                                    h->ntot, src, launch_grid(h), s);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+lb_status build_graph(lbb_handle* h, int start)
+{
+    if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+    lb_status st = LB_OK;
+    int src = start;
+    for (int k = 0; k < h->graph_steps && st == LB_OK; ++k) {
+        st = launch_one(h, h->capture, src);
+        src ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->capture, &g);
+    if (st != LB_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return fail(LB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->exec[start], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+lb_status run_sums(lbb_handle* h, int k, int* flag)
+{
+    const Lat& a = h->lats[k];
+    (void)a;
+    hipError_t e = lbk::launch_sums(h->storage, h->base, h->d_desc() + k, h->cur, lbk::sums_blocks(),
+                                    h->d_part(), h->d_res(), flag, h->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "sums launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+lb_status steps(lbb_handle* h, int32_t n)
+{
+    if (n < 0) return fail(LB_EINVAL, "negative step count");
+    while (n > 0) {
+        int chunk = n;
+        if (h->watchdog > 0) {
+            const int64_t to_next = h->watchdog - (h->t % h->watchdog);
+            chunk = (int)std::min<int64_t>(chunk, to_next);
+        }
+        if (h->graph_steps > 0 && chunk >= h->graph_steps) {
+            const int reps = chunk / h->graph_steps;
+            if (!h->exec[h->cur]) {
+                lb_status st = build_graph(h, h->cur);
+                if (st != LB_OK) return st;
+            }
+            for (int r = 0; r < reps; ++r)
+                HIP_TRY(hipGraphLaunch(h->exec[h->cur], h->stream));
+            // graph_steps is even, so the buffer parity is unchanged
+            const int done = reps * h->graph_steps;
+            h->t += done;
+            h->nsamples += done;
+            n -= done;
+            chunk -= done;
+        }
+        for (int k = 0; k < chunk; ++k) {
+            lb_status st = launch_one(h, h->stream, h->cur);
+            if (st != LB_OK) return st;
+            h->cur ^= 1;
+            h->t += 1;
+            h->nsamples += 1;
+        }
+        n -= chunk;
+        if (h->watchdog > 0 && h->t % h->watchdog == 0)
+            for (size_t k = 0; k < h->lats.size(); ++k) {
+                lb_status st = run_sums(h, (int)k, h->d_flag());
+                if (st != LB_OK) return st;
+            }
+    }
+    return LB_OK;
+}
+
+lb_status check_flag(lbb_handle* h)
+{
+    int f = 0;
+    HIP_TRY(hipMemcpyAsync(&f, h->d_flag(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (f) return fail(LB_ENONFINITE, "watchdog: non-finite or non-positive density in the lattice");
+    return LB_OK;
+}
+
+lb_status reset_acc(lbb_handle* h)
+{
+    for (const Lat& a : h->lats) {
+        HIP_TRY(lbk::launch_fill((double*)(h->base + a.off_stress), 2ll * a.p.nx, 0.0, h->stream));
+        if (a.p.profile)
+            HIP_TRY(lbk::launch_fill((double*)(h->base + a.off_prof), (long long)a.ngroups * a.p.ny, 0.0,
+                                     h->stream));
+    }
+    h->nsamples = 0;
+    return LB_OK;
+}
+
+lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t bytes, void* stream,
+                     const double* const* ra, const double* const* rb, const double* const* ux,
+                     const double* const* uy, lbb_handle** out)
+{
+    if (!out) return fail(LB_EINVAL, "null output handle");
+    *out = nullptr;
+    if (n < 1 || !params) return fail(LB_EINVAL, "need at least one lattice");
+    if (!dev_state) return fail(LB_EINVAL, "null device state");
+    if (((uintptr_t)dev_state) % ALIGN) return fail(LB_EINVAL, "device state must be 256-byte aligned");
+    if (!ra || !rb) return fail(LB_EINVAL, "null initial density arrays");
+    std::vector<Lat> lats(n);
+    for (int k = 0; k < n; ++k) {
+        lb_status st = validate(&params[k], params[0].storage);
+        if (st != LB_OK) return st;
+        lats[k].p = params[k];
+        if (!ra[k] || !rb[k]) return fail(LB_EINVAL, "null initial density of lattice %d", k);
+        const size_t ns = (size_t)params[k].nx * params[k].ny;
+        double sum[2] = {0, 0};
+        for (size_t i = 0; i < ns; ++i) {
+            const double a = ra[k][i], b = rb[k][i];
+            if (!(a > 0.0) || !(b > 0.0) || !std::isfinite(a) || !std::isfinite(b))
+                return fail(LB_EINVAL, "lattice %d: initial density must be finite and > 0 (site %zu)", k, i);
+            sum[0] += a;
+            sum[1] += b;
+            if (ux && ux[k] && !std::isfinite(ux[k][i])) return fail(LB_EINVAL, "non-finite initial ux");
+            if (uy && uy[k] && !std::isfinite(uy[k][i])) return fail(LB_EINVAL, "non-finite initial uy");
+        }
+        lats[k].rho_ref[0] = params[k].rho_ref_a > 0 ? params[k].rho_ref_a : sum[0] / ns;
+        lats[k].rho_ref[1] = params[k].rho_ref_b > 0 ? params[k].rho_ref_b : sum[1] / ns;
+    }
+    Layout lay = plan(lats);
+    if (bytes < lay.total)
+        return fail(LB_ENOMEM, "device state of %zu bytes is smaller than the %zu required", bytes, lay.total);
+
+    lbb_handle* h = new (std::nothrow) lbb_handle();
+    if (!h) return fail(LB_ENOMEM, "host allocation failed");
+    h->lats = lats;
+    h->lay = lay;
+    h->storage = params[0].storage;
+    h->base = (char*)dev_state;
+    h->bytes = bytes;
+    h->stream = (hipStream_t)stream;
+    h->descs.resize(n);
+    for (int k = 0; k < n; ++k) fill_desc(lats[k], h->descs[k]);
+    // Default launch shape: 256 columns per block where the lattices are wide enough.
+    int maxnx = 0;
+    for (const Lat& a : lats) maxnx = std::max(maxnx, a.p.nx);
+    h->bx = maxnx >= 256 ? 256 : (maxnx >= 128 ? 128 : 64);
+    h->ly = 64;
+    lb_status st = decompose(h);
+    if (st != LB_OK) { delete h; return st; }
+
+    // Stage each lattice's initial fields in its second population buffer
+    // (at least 32 bytes per site in every storage format), then write f(0).
+    for (int k = 0; k < n; ++k) {
+        const Lat& a = h->lats[k];
+        const size_t ns = (size_t)a.p.nx * a.p.ny;
+        double* stg = (double*)(h->base + a.off_f[1]);
+        const double* src[4] = {ra[k], rb[k], ux ? ux[k] : nullptr, uy ? uy[k] : nullptr};
+        double* dst[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int m = 0; m < 4; ++m)
+            if (src[m]) {
+                dst[m] = stg + m * ns;
+                hipError_t e = hipMemcpyAsync(dst[m], src[m], ns * sizeof(double), hipMemcpyHostToDevice, h->stream);
+                if (e != hipSuccess) { delete h; return fail(LB_EDEVICE, "upload failed: %s", hipGetErrorString(e)); }
+            }
+        hipError_t e = lbk::launch_init(h->storage, h->base, h->d_desc() + k, (long long)ns, 0, dst[0], dst[1],
+                                        dst[2], dst[3], h->stream);
+        if (e != hipSuccess) { delete h; return fail(LB_EDEVICE, "init launch failed: %s", hipGetErrorString(e)); }
+    }
+    HIP_TRY(lbk::launch_fill((double*)(h->base + lay.off_res), 8 + 2 * n, 0.0, h->stream));
+    st = reset_acc(h);
+    if (st != LB_OK) { delete h; return st; }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) { delete h; return fail(LB_EDEVICE, "init failed: %s", hipGetErrorString(e)); }
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lattice_fields(lbb_handle* h, int k, double* ra, double* rb, double* ux, double* uy, bool host)
+{
+    if (k < 0 || k >= (int)h->lats.size()) return fail(LB_EINVAL, "lattice index out of range");
+    const Lat& a = h->lats[k];
+    const size_t ns = (size_t)a.p.nx * a.p.ny;
+    if (!host) {
+        HIP_TRY(lbk::launch_fields(h->storage, h->base, h->d_desc() + k, (long long)ns, h->cur, ra, rb, ux, uy,
+                                   h->stream));
+        return LB_OK;
+    }
+    // compute into the idle population buffer, then copy out
+    double* stg = (double*)(h->base + a.off_f[h->cur ^ 1]);
+    double* outs[4] = {ra, rb, ux, uy};
+    double* dev[4];
+    for (int m = 0; m < 4; ++m) dev[m] = outs[m] ? stg + m * ns : nullptr;
+    HIP_TRY(lbk::launch_fields(h->storage, h->base, h->d_desc() + k, (long long)ns, h->cur, dev[0], dev[1],
+                               dev[2], dev[3], h->stream));
+    for (int m = 0; m < 4; ++m)
+        if (outs[m]) HIP_TRY(hipMemcpyAsync(outs[m], dev[m], ns * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+lb_status stress_all(lbb_handle* h, double* sb, double* stp, int64_t* ns)
+{
+    const int n = (int)h->lats.size();
+    double* dres = h->d_res() + 8;
+    HIP_TRY(lbk::launch_stress_reduce(h->base, h->d_desc(), n, dres, h->stream));
+    std::vector<double> r(2 * n);
+    HIP_TRY(hipMemcpyAsync(r.data(), dres, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < n; ++k) {
+        const double nx = h->lats[k].p.nx;
+        const double m = h->nsamples > 0 ? (double)h->nsamples : 1.0;
+        const double vb = h->nsamples > 0 ? r[2 * k] / nx / m : 0.0;
+        const double vt = h->nsamples > 0 ? -r[2 * k + 1] / nx / m : 0.0;
+        if (sb) sb[k] = vb;
+        if (stp) stp[k] = vt;
+    }
+    if (ns) *ns = h->nsamples;
+    return LB_OK;
+}
+
+lb_status profile_one(lbb_handle* h, int k, double* prof, int64_t* ns)
+{
+    if (k < 0 || k >= (int)h->lats.size()) return fail(LB_EINVAL, "lattice index out of range");
+    const Lat& a = h->lats[k];
+    if (!a.p.profile) return fail(LB_ESTATE, "profile accumulation was not enabled (lb_params.profile)");
+    if (!prof) return fail(LB_EINVAL, "null profile array");
+    double* stg = (double*)(h->base + a.off_f[h->cur ^ 1]);
+    HIP_TRY(lbk::launch_profile_reduce(h->base, h->d_desc() + k, a.p.ny, stg, h->stream));
+    HIP_TRY(hipMemcpyAsync(prof, stg, sizeof(double) * a.p.ny, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double m = h->nsamples > 0 ? (double)h->nsamples * a.p.nx : 1.0;
+    for (int y = 0; y < a.p.ny; ++y) prof[y] = h->nsamples > 0 ? prof[y] / m : 0.0;
+    if (ns) *ns = h->nsamples;
+    return LB_OK;
+}
+
+lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
+{
+    if (bx != 0 && bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "bx must be 64, 128 or 256");
+    if (ly < 0) return fail(LB_EINVAL, "ly must be >= 0");
+    if (grid < 0) return fail(LB_EINVAL, "grid must be >= 0");
+    if (bx) h->bx = bx;
+    if (ly) h->ly = ly;
+    h->grid = grid;
+    return decompose(h);
+}
+
+lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
+{
+    if (n < 1 || !ms) return fail(LB_EINVAL, "need n >= 1 and an output");
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(hipEventRecord(a, h->stream));
+    lb_status st = steps(h, n);
+    HIP_TRY(hipEventRecord(b, h->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != LB_OK) return st;
+    *ms = (double)t / n;
+    return LB_OK;
+}
+
+void destroy_batch(lbb_handle* h)
+{
+    drop_graphs(h);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    delete h;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI ---
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+lb_status lb_state_bytes(const lb_params* p, size_t* bytes) { return lbb_state_bytes(p, 1, bytes); }
+
+lb_status lbb_state_bytes(const lb_params* params, int32_t n, size_t* bytes)
+{
+    if (!bytes || !params || n < 1) return fail(LB_EINVAL, "bad arguments");
+    std::vector<Lat> lats(n);
+    for (int k = 0; k < n; ++k) {
+        lb_status st = validate(&params[k], params[0].storage);
+        if (st != LB_OK) return st;
+        lats[k].p = params[k];
+    }
+    *bytes = plan(lats).total;
+    return LB_OK;
+}
+
+lb_status lb_init(const lb_params* p, void* dev_state, size_t bytes, void* hip_stream, const double* rho_a,
+                  const double* rho_b, const double* ux, const double* uy, lb_handle** out)
+{
+    if (!out) return fail(LB_EINVAL, "null output handle");
+    *out = nullptr;
+    const double* ra[1] = {rho_a};
+    const double* rb[1] = {rho_b};
+    const double* u[1] = {ux};
+    const double* v[1] = {uy};
+    lbb_handle* b = nullptr;
+    lb_status st = batch_init(p, 1, dev_state, bytes, hip_stream, ra, rb, u, v, &b);
+    if (st != LB_OK) return st;
+    lb_handle* h = new (std::nothrow) lb_handle();
+    if (!h) { destroy_batch(b); return fail(LB_ENOMEM, "host allocation failed"); }
+    h->b = std::move(*b);
+    b->exec[0] = b->exec[1] = nullptr;
+    b->capture = nullptr;
+    delete b;
+    *out = h;
+    return LB_OK;
+}
+
+#define CHECK_H(h) \
+    if (!(h)) return fail(LB_EINVAL, "null handle")
+
+lb_status lb_step(lb_handle* h, int32_t n)
+{
+    CHECK_H(h);
+    return steps(&h->b, n);
+}
+
+lb_status lb_fields(lb_handle* h, double* ra, double* rb, double* ux, double* uy)
+{
+    CHECK_H(h);
+    lb_status st = lattice_fields(&h->b, 0, ra, rb, ux, uy, true);
+    if (st != LB_OK) return st;
+    return check_flag(&h->b);
+}
+
+lb_status lb_fields_device(lb_handle* h, double* ra, double* rb, double* ux, double* uy)
+{
+    CHECK_H(h);
+    return lattice_fields(&h->b, 0, ra, rb, ux, uy, false);
+}
+
+lb_status lb_populations(lb_handle* h, double* f)
+{
+    CHECK_H(h);
+    if (!f) return fail(LB_EINVAL, "null output");
+    lbb_handle* b = &h->b;
+    const Lat& a = b->lats[0];
+    const size_t ns = (size_t)a.p.nx * a.p.ny;
+    double* stg = (double*)(b->base + a.off_f[b->cur ^ 1]);
+    for (int q = 0; q < 18; ++q) {
+        HIP_TRY(lbk::launch_export(b->storage, b->base, b->d_desc(), (long long)ns, b->cur, q, stg, b->stream));
+        HIP_TRY(hipMemcpyAsync(f + q * ns, stg, ns * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return LB_OK;
+}
+
+lb_status lb_stress(lb_handle* h, double* sb, double* stp, int64_t* ns)
+{
+    CHECK_H(h);
+    lb_status st = stress_all(&h->b, sb, stp, ns);
+    if (st != LB_OK) return st;
+    return check_flag(&h->b);
+}
+
+lb_status lb_stress_reset(lb_handle* h)
+{
+    CHECK_H(h);
+    return reset_acc(&h->b);
+}
+
+lb_status lb_profile(lb_handle* h, double* prof, int64_t* ns)
+{
+    CHECK_H(h);
+    return profile_one(&h->b, 0, prof, ns);
+}
+
+lb_status lb_sums(lb_handle* h, double out[5])
+{
+    CHECK_H(h);
+    if (!out) return fail(LB_EINVAL, "null output");
+    lbb_handle* b = &h->b;
+    lb_status st = run_sums(b, 0, b->d_flag());
+    if (st != LB_OK) return st;
+    HIP_TRY(hipMemcpyAsync(out, b->d_res(), 5 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (out[4] > 0) return fail(LB_ENONFINITE, "%g sites with a non-finite or non-positive density", out[4]);
+    return check_flag(b);
+}
+
+lb_status lb_set_watchdog(lb_handle* h, int32_t every)
+{
+    CHECK_H(h);
+    if (every < 0) return fail(LB_EINVAL, "watchdog interval must be >= 0");
+    h->b.watchdog = every;
+    return LB_OK;
+}
+
+lb_status lb_set_launch(lb_handle* h, int32_t bx, int32_t ly)
+{
+    CHECK_H(h);
+    return set_launch(&h->b, bx, ly, 0);
+}
+
+lb_status lb_set_graph(lb_handle* h, int32_t k)
+{
+    CHECK_H(h);
+    if (k < 0 || (k % 2)) return fail(LB_EINVAL, "steps per graph must be 0 or a positive even number");
+    h->b.graph_steps = k;
+    drop_graphs(&h->b);
+    return LB_OK;
+}
+
+// Checkpoint format: header, then the current population buffer in its
+// storage format, then the FP64 stress and profile accumulators.
+struct CkptHeader {
+    char magic[8];
+    int32_t version, storage, nx, ny, pitch, profile;
+    int64_t t, nsamples;
+    uint64_t fbytes, sbytes, pbytes;
+};
+
+lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
+{
+    CHECK_H(h);
+    if (!bytes) return fail(LB_EINVAL, "null size");
+    lbb_handle* b = &h->b;
+    const Lat& a = b->lats[0];
+    const size_t fb = 18ull * a.plane * storage_size(b->storage);
+    const size_t sbb = 2ull * a.p.nx * sizeof(double);
+    const size_t pb = a.p.profile ? (size_t)a.ngroups * a.p.ny * sizeof(double) : 0;
+    const size_t need = sizeof(CkptHeader) + fb + sbb + pb;
+    if (!buf) { *bytes = need; return LB_OK; }
+    if (*bytes < need) return fail(LB_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, "LBMI355", 8);
+    hd.version = 1;
+    hd.storage = b->storage;
+    hd.nx = a.p.nx;
+    hd.ny = a.p.ny;
+    hd.pitch = a.pitch;
+    hd.profile = a.p.profile;
+    hd.t = b->t;
+    hd.nsamples = b->nsamples;
+    hd.fbytes = fb;
+    hd.sbytes = sbb;
+    hd.pbytes = pb;
+    char* p = (char*)buf;
+    std::memcpy(p, &hd, sizeof hd);
+    HIP_TRY(hipMemcpyAsync(p + sizeof hd, b->base + a.off_f[b->cur], fb, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(p + sizeof hd + fb, b->base + a.off_stress, sbb, hipMemcpyDeviceToHost, b->stream));
+    if (pb) HIP_TRY(hipMemcpyAsync(p + sizeof hd + fb + sbb, b->base + a.off_prof, pb, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    *bytes = need;
+    return LB_OK;
+}
+
+lb_status lb_load(lb_handle* h, const void* buf, size_t bytes)
+{
+    CHECK_H(h);
+    if (!buf || bytes < sizeof(CkptHeader)) return fail(LB_EINVAL, "checkpoint buffer too small");
+    lbb_handle* b = &h->b;
+    const Lat& a = b->lats[0];
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, "LBMI355", 8) != 0 || hd.version != 1) return fail(LB_ESTATE, "not a checkpoint");
+    if (hd.storage != b->storage || hd.nx != a.p.nx || hd.ny != a.p.ny || hd.pitch != a.pitch ||
+        hd.profile != a.p.profile)
+        return fail(LB_ESTATE, "checkpoint of another lattice shape, storage or profile setting");
+    if (bytes < sizeof hd + hd.fbytes + hd.sbytes + hd.pbytes) return fail(LB_EINVAL, "truncated checkpoint");
+    const char* p = (const char*)buf;
+    b->cur = 0;
+    HIP_TRY(hipMemcpyAsync(b->base + a.off_f[0], p + sizeof hd, hd.fbytes, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->base + a.off_stress, p + sizeof hd + hd.fbytes, hd.sbytes, hipMemcpyHostToDevice,
+                           b->stream));
+    if (hd.pbytes)
+        HIP_TRY(hipMemcpyAsync(b->base + a.off_prof, p + sizeof hd + hd.fbytes + hd.sbytes, hd.pbytes,
+                               hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->t = hd.t;
+    b->nsamples = hd.nsamples;
+    return LB_OK;
+}
+
+lb_status lb_time(lb_handle* h, int64_t* t)
+{
+    CHECK_H(h);
+    if (!t) return fail(LB_EINVAL, "null output");
+    *t = h->b.t;
+    return LB_OK;
+}
+
+lb_status lb_time_steps(lb_handle* h, int32_t n, double* ms)
+{
+    CHECK_H(h);
+    return time_steps(&h->b, n, ms);
+}
+
+lb_status lb_destroy(lb_handle* h)
+{
+    if (!h) return LB_OK;
+    drop_graphs(&h->b);
+    if (h->b.capture) (void)hipStreamDestroy(h->b.capture);
+    delete h;
+    return LB_OK;
+}
+
+// ----------------------------------------------------------------- batch ---
+
+lb_status lbb_init(const lb_params* params, int32_t n, void* dev_state, size_t bytes, void* hip_stream,
+                   const double* const* rho_a, const double* const* rho_b, const double* const* ux,
+                   const double* const* uy, lbb_handle** out)
+{
+    return batch_init(params, n, dev_state, bytes, hip_stream, rho_a, rho_b, ux, uy, out);
+}
+
+lb_status lbb_step(lbb_handle* h, int32_t n)
+{
+    CHECK_H(h);
+    return steps(h, n);
+}
+
+lb_status lbb_stress(lbb_handle* h, double* sb, double* stp, int64_t* ns)
+{
+    CHECK_H(h);
+    lb_status st = stress_all(h, sb, stp, ns);
+    if (st != LB_OK) return st;
+    return check_flag(h);
+}
+
+lb_status lbb_stress_reset(lbb_handle* h)
+{
+    CHECK_H(h);
+    return reset_acc(h);
+}
+
+lb_status lbb_fields(lbb_handle* h, int32_t k, double* ra, double* rb, double* ux, double* uy)
+{
+    CHECK_H(h);
+    return lattice_fields(h, k, ra, rb, ux, uy, true);
+}
+
+lb_status lbb_profile(lbb_handle* h, int32_t k, double* prof, int64_t* ns)
+{
+    CHECK_H(h);
+    return profile_one(h, k, prof, ns);
+}
+
+lb_status lbb_set_launch(lbb_handle* h, int32_t bx, int32_t ly, int32_t grid)
+{
+    CHECK_H(h);
+    return set_launch(h, bx, ly, grid);
+}
+
+lb_status lbb_set_graph(lbb_handle* h, int32_t k)
+{
+    CHECK_H(h);
+    if (k < 0 || (k % 2)) return fail(LB_EINVAL, "steps per graph must be 0 or a positive even number");
+    h->graph_steps = k;
+    drop_graphs(h);
+    return LB_OK;
+}
+
+lb_status lbb_time_steps(lbb_handle* h, int32_t n, double* ms)
+{
+    CHECK_H(h);
+    return time_steps(h, n, ms);
+}
+
+lb_status lbb_destroy(lbb_handle* h)
+{
+    if (!h) return LB_OK;
+    destroy_batch(h);
+    return LB_OK;
+}
+
+}  // extern "C"

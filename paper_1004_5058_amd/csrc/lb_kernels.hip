@@ -1,0 +1,689 @@
+// HIP kernels (gfx950) of the two-species multirange Shan-Chen lattice
+// Boltzmann step: Eq. (1) with the velocity-shift forcing, the forces of
+// Eq. (2) on the 24-offset stencil of Fig. 1, and the pseudo-potential
+// psi = rho0 (1 - exp(-rho/rho0)) (section "Lattice Boltzmann with multirange
+// interactions" of arXiv:1004.5058).
+//
+// The step kernel is one fused pass per time step over populations stored
+// structure-of-arrays, f[s][i][y][x] with x fastest:
+//   * a block owns a strip of BX columns (one thread per column) and marches
+//     down a segment of ly rows;
+//   * for the row two ahead of the one it collides, each thread loads its
+//     18 populations (aligned, coalesced), sums the two densities and stores
+//     (psi_A, psi_B, rho_A, rho_B) in a six-row LDS ring; four lanes of wave 0
+//     do the same for the two halo columns on each side;
+//   * after one barrier the thread collides its centre row with the force read
+//     from the 5x5 LDS neighbourhood and pushes the 18 post-collision
+//     populations to their neighbours (row y-1, y, y+1 of the other buffer),
+//     bouncing back at the walls and summing the wall momentum per column in
+//     FP64.
+// The three population rows in flight live in registers, so every
+// population is read once and written once per step; the only re-reads are
+// the halo columns and the two halo rows at each end of a segment.
+#include "lb_device.hpp"
+#include "lb_kernels.hpp"
+
+namespace lbk {
+
+// ---------------------------------------------------------------- storage --
+
+// Every format stores the deviation d_is = f_is - w_i rho_ref_s of a population
+// from the rest equilibrium at the lattice's reference densities; arithmetic
+// is FP64 for FP64 storage and FP32 otherwise.
+struct StF64 { using S = double;   using C = double; };
+struct StF32 { using S = float;    using C = float; };
+struct StF16 { using S = _Float16; using C = float; };
+struct StBF16 { using S = __bf16;  using C = float; };
+
+template <class C> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+
+// Raw buffer access.  A block addresses each species' plane stack through a
+// buffer resource: the per-lane column byte offset is the VGPR offset and the
+// uniform (direction, row) byte offset is the SGPR offset, so the 18 loads and
+// 18 stores of a row need no 64-bit address arithmetic.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, RSRC_WORD3);
+}
+
+template <class S> __device__ __forceinline__ S bload(rsrc_t r, unsigned voff, int soff);
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, int soff)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(double, (u2)__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, int soff)
+{
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ __bf16 bload<__bf16>(rsrc_t r, unsigned voff, int soff)
+{
+    return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+
+template <class S> __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned voff, int soff);
+template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, unsigned voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff, int soff)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ void bstore<_Float16>(_Float16 v, rsrc_t r, unsigned voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ void bstore<__bf16>(__bf16 v, rsrc_t r, unsigned voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+}
+
+// Load / store one deviation, converting between the storage and the
+// arithmetic type (round to nearest even on the way down).
+template <class P>
+__device__ __forceinline__ typename P::C ld(rsrc_t r, unsigned voff, int soff)
+{
+    return (typename P::C)bload<typename P::S>(r, voff, soff);
+}
+
+template <class P>
+__device__ __forceinline__ void st(rsrc_t r, unsigned voff, int soff, typename P::C v)
+{
+    bstore<typename P::S>((typename P::S)v, r, voff, soff);
+}
+
+// Deviation of the pseudo-potential from its value at the reference density:
+// psi(rho_ref + d) - psi(rho_ref) = -E expm1(-d/rho0), E = rho0 exp(-rho_ref/rho0).
+__device__ __forceinline__ float dpsi_of(float d, float e, float inv_rho0)
+{
+    return -e * expm1f(-d * inv_rho0);
+}
+__device__ __forceinline__ double dpsi_of(double d, double e, double inv_rho0)
+{
+    return -e * expm1(-d * inv_rho0);
+}
+
+// Reciprocal: the hardware approximation (<= 1 ulp) in FP32, exact division in FP64.
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class P>
+__device__ __forceinline__ int map_row(int r, int ny, int walls)
+{
+    if (walls) {
+        if (r < 0) r = -1 - r;
+        else if (r >= ny) r = 2 * ny - 1 - r;
+    } else {
+        r %= ny;
+        if (r < 0) r += ny;
+    }
+    return r;
+}
+
+// ------------------------------------------------------------------ step ---
+
+template <int BX, class P>
+__global__ void __launch_bounds__(BX)
+k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int ntot, int src)
+{
+    using S = typename P::S;
+    using C = typename P::C;
+    using C4 = typename V4<C>::T;
+    __shared__ C4 ring[6][BX + 4];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+
+    for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
+        int L = 0;
+        for (int k = 1; k < nlat; ++k)
+            if (descs[k].item_begin <= w) L = k;
+        const LatDesc& d = descs[L];
+        const int l = w - d.item_begin;
+        if (l >= d.nitems) continue;
+        int lin = l;
+        if ((d.nitems & 7) == 0) {       // keep neighbouring tiles on one XCD
+            const int c = d.nitems >> 3;
+            lin = (l & 7) * c + (l >> 3);
+        }
+        const int nstrip = d.nstrip;
+        const int strip = lin % nstrip, seg = lin / nstrip;
+        const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
+        const long long plane = d.plane;
+        const int x0 = strip * BX;
+        const int y0 = seg * d.ly;
+        const int y1 = min(y0 + d.ly, ny);
+        const unsigned x = (unsigned)(x0 + tid);
+        const bool valid = x < (unsigned)nx;
+        const unsigned xc = x % (unsigned)nx;
+        const unsigned xp = (xc + 1 == (unsigned)nx) ? 0u : xc + 1;
+        const unsigned xm = (xc == 0) ? (unsigned)(nx - 1) : xc - 1;
+        unsigned hcol = 0;
+        int hidx = 0;
+        if (tid < 4) {
+            int hc = (tid < 2) ? x0 - 2 + tid : x0 + BX + tid - 2;
+            hc %= nx;
+            if (hc < 0) hc += nx;
+            hcol = (unsigned)hc;
+            hidx = (tid < 2) ? tid : BX + tid;
+        }
+
+        const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
+        const C rho0 = coef<C>(d.rho0, d.frho0), inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
+        C ks0[5], ks1[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            ks0[k] = coef<C>(d.ks[0][k], d.fks[0][k]);
+            ks1[k] = coef<C>(d.ks[1][k], d.fks[1][k]);
+        }
+        const C kx1 = coef<C>(d.kx[0], d.fkx[0]), kx2 = coef<C>(d.kx[1], d.fkx[1]);
+        const C u_top = coef<C>(d.u_top, d.fu_top), u_bot = coef<C>(d.u_bot, d.fu_bot);
+        const C rref0 = coef<C>(d.rref[0], d.frref[0]), rref1 = coef<C>(d.rref[1], d.frref[1]);
+        const C pref0 = coef<C>(d.psiref[0], d.fpsiref[0]), pref1 = coef<C>(d.psiref[1], d.fpsiref[1]);
+        const C e0 = coef<C>(d.epsi[0], d.fepsi[0]), e1 = coef<C>(d.epsi[1], d.fepsi[1]);
+
+        // One buffer resource per species and buffer; byte offsets stay below 2^32.
+        const unsigned sbytes = (unsigned)(9 * plane * (long long)sizeof(S));
+        const char* fin = base + d.off_f[src];
+        const char* fout = base + d.off_f[src ^ 1];
+        const rsrc_t rin0 = make_rsrc(fin, sbytes), rin1 = make_rsrc(fin + sbytes, sbytes);
+        const rsrc_t rout0 = make_rsrc(fout, sbytes), rout1 = make_rsrc(fout + sbytes, sbytes);
+        const int es = (int)sizeof(S);
+        const unsigned vc = xc * es, vp = xp * es, vm = xm * es, vh = hcol * es;
+        const int pbytes = (int)(plane * es), rbytes = pitch * es;
+        double* __restrict__ stress = (double*)(base + d.off_stress);
+        double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
+
+        // Load row r's populations into fr, stage (psi, rho) of row r in LDS.
+        auto stage = [&](C(&fr)[18], int r) {
+            const int rr = map_row<P>(r, ny, walls);
+            const int slot = (r - y0 + 2) % 6;
+            const int so = rr * rbytes;
+#pragma unroll
+            for (int q = 0; q < 18; ++q)
+                fr[q] = ld<P>(q < 9 ? rin0 : rin1, vc, so + (q % 9) * pbytes);
+            C ra = fr[0], rb = fr[9];
+#pragma unroll
+            for (int q = 1; q < 9; ++q) { ra += fr[q]; rb += fr[9 + q]; }
+            C4 v;
+            v.x = dpsi_of(ra, e0, inv_rho0);
+            v.y = dpsi_of(rb, e1, inv_rho0);
+            v.z = ra;
+            v.w = rb;
+            ring[slot][tid + 2] = v;
+            if (tid < 4) {
+                C h[18];
+#pragma unroll
+                for (int q = 0; q < 18; ++q)
+                    h[q] = ld<P>(q < 9 ? rin0 : rin1, vh, so + (q % 9) * pbytes);
+                C ha = h[0], hb = h[9];
+#pragma unroll
+                for (int q = 1; q < 9; ++q) { ha += h[q]; hb += h[9 + q]; }
+                C4 hv;
+                hv.x = dpsi_of(ha, e0, inv_rho0);
+                hv.y = dpsi_of(hb, e1, inv_rho0);
+                hv.z = ha;
+                hv.w = hb;
+                ring[slot][hidx] = hv;
+            }
+        };
+
+        // Collide row y (populations in f, neighbourhood in LDS) and push.
+        auto collide = [&](const C(&f)[18], int y) {
+            int sl[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sl[k] = (y - 2 + k - y0 + 2) % 6;
+            C sxA = 0, syA = 0, sxB = 0, syB = 0, cxA = 0, cyA = 0, cxB = 0, cyB = 0;
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const C4 n = ring[sl[dy + 2]][tid + 2 + dx];
+                    const int sh = shell_of(dx, dy);
+                    if (dx != 0) {
+                        sxA += (ks0[sh] * (C)dx) * n.x;
+                        sxB += (ks1[sh] * (C)dx) * n.y;
+                    }
+                    if (dy != 0) {
+                        syA += (ks0[sh] * (C)dy) * n.x;
+                        syB += (ks1[sh] * (C)dy) * n.y;
+                    }
+                    if (sh <= 1) {
+                        const C kk = (sh == 0) ? kx1 : kx2;
+                        if (dx != 0) { cxA += (kk * (C)dx) * n.w; cxB += (kk * (C)dx) * n.z; }
+                        if (dy != 0) { cyA += (kk * (C)dy) * n.w; cyB += (kk * (C)dy) * n.z; }
+                    }
+                }
+            }
+            const C4 c0 = ring[sl[2]][tid + 2];
+            // absolute densities and potentials of the centre site
+            const C ra = rref0 + c0.z, rb = rref1 + c0.w;
+            const C pa = pref0 + c0.x, pb = pref1 + c0.y;
+            const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
+            const C FxB = -pb * sxB - rb * cxB, FyB = -pb * syB - rb * cyB;
+
+            const C jx = (f[1] - f[3] + f[5] - f[6] - f[7] + f[8])
+                       + (f[10] - f[12] + f[14] - f[15] - f[16] + f[17]);
+            const C jy = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8])
+                       + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
+            const C inv_rho = rcp(ra + rb);
+            const C ux = jx * inv_rho, uy = jy * inv_rho;
+
+            C fs[18];
+            // BGK relaxation of the deviations towards
+            // f^eq_i - w_i rho_ref = w_i [drho + rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)]
+            auto relax = [&](int s, C rs, C drs, C Fx, C Fy) {
+                const C inv = rcp(rs);
+                const C vx = ux + tau * Fx * inv;
+                const C vy = uy + tau * Fy * inv;
+                const C usq = (C)1.5 * (vx * vx + vy * vy);
+                const C r0 = rs * (C)(4.0 / 9.0), r1 = rs * (C)(1.0 / 9.0), r2 = rs * (C)(1.0 / 36.0);
+                const C d1 = drs * (C)(1.0 / 9.0), d2 = drs * (C)(1.0 / 36.0);
+                const int o = 9 * s;
+                fs[o + 0] = f[o + 0] - omega * (f[o + 0] - (drs * (C)(4.0 / 9.0) - r0 * usq));
+                auto pair = [&](int ip, int im, C rw, C dw, C cu) {
+                    const C sym = dw + rw * ((C)4.5 * cu * cu - usq);
+                    const C anti = rw * ((C)3 * cu);
+                    fs[o + ip] = f[o + ip] - omega * (f[o + ip] - (sym + anti));
+                    fs[o + im] = f[o + im] - omega * (f[o + im] - (sym - anti));
+                };
+                pair(1, 3, r1, d1, vx);
+                pair(2, 4, r1, d1, vy);
+                pair(5, 7, r2, d2, vx + vy);
+                pair(6, 8, r2, d2, vy - vx);
+            };
+            relax(0, ra, c0.z, FxA, FyA);
+            relax(1, rb, c0.w, FxB, FyB);
+
+            if (prof != nullptr && x0 + 64 * wave < nx) {    // wave-uniform condition
+                double s = valid ? (double)ux : 0.0;
+                s = wave_sum(s);
+                if ((tid & 63) == 0) {
+                    double* pp = prof + (long long)(x0 / 64 + wave) * ny + y;
+                    *pp += s;
+                }
+            }
+            if (!valid) return;
+
+            const bool bot = walls && (y == 0);
+            const bool top = walls && (y == ny - 1);
+            C mom_b = 0, mom_t = 0;
+#pragma unroll
+            for (int q = 0; q < 18; ++q) {
+                const int s = q / 9, i = q % 9;
+                const int cx = CX[i], cy = CY[i];
+                const C rs = (s == 0) ? ra : rb;
+                const rsrc_t ro = (s == 0) ? rout0 : rout1;
+                if (cy < 0 && bot) {
+                    const C back = (cx != 0) ? fs[q] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[q];
+                    st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
+                    if (cx != 0) mom_b += (C)cx * (fs[q] + back);
+                } else if (cy > 0 && top) {
+                    const C back = (cx != 0) ? fs[q] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[q];
+                    st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
+                    if (cx != 0) mom_t += (C)cx * (fs[q] + back);
+                } else {
+                    int yt = y + cy;
+                    if (yt < 0) yt += ny;
+                    else if (yt >= ny) yt -= ny;
+                    const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
+                    st<P>(ro, vcol, i * pbytes + yt * rbytes, fs[q]);
+                }
+            }
+            if (bot) stress[xc] += (double)mom_b;
+            if (top) stress[nx + xc] += (double)mom_t;
+        };
+
+        C F0[18], F1[18], F2[18];
+        stage(F2, y0 - 2);
+        stage(F2, y0 - 1);
+        stage(F0, y0);
+        stage(F1, y0 + 1);
+        for (int y = y0; y < y1; y += 3) {
+            stage(F2, y + 2);
+            __syncthreads();
+            collide(F0, y);
+            if (y + 1 < y1) {
+                stage(F0, y + 3);
+                __syncthreads();
+                collide(F1, y + 1);
+            }
+            if (y + 2 < y1) {
+                stage(F1, y + 4);
+                __syncthreads();
+                collide(F2, y + 2);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- auxiliary ---
+
+template <class P>
+__device__ __forceinline__ double decode(const typename P::S* p, const LatDesc& d, int q)
+{
+    return d.wref[q] + (double)*p;
+}
+
+// f_is(r, 0) = f^eq_i(rho_s(r), u(r)), evaluated in FP64 and rounded once to
+// the storage format.
+template <class P>
+__global__ void k_init(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf,
+                       const double* __restrict__ ra, const double* __restrict__ rb,
+                       const double* __restrict__ ux, const double* __restrict__ uy)
+{
+    using S = typename P::S;
+    using C = typename P::C;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    S* f = (S*)(base + d.off_f[buf]);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        const double u = ux ? ux[k] : 0.0, v = uy ? uy[k] : 0.0;
+        const double uu = u * u + v * v;
+        S* out = f + (long long)y * d.pitch + x;
+        for (int s = 0; s < 2; ++s) {
+            const double rho = s == 0 ? ra[k] : rb[k];
+            for (int i = 0; i < 9; ++i) {
+                const double cu = CX[i] * u + CY[i] * v;
+                const double feq = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                out[(9 * s + i) * d.plane] = (S)(C)(feq - d.wref[9 * s + i]);
+            }
+        }
+    }
+}
+
+// Densities and barycentric velocity of the stored populations, in FP64.
+template <class P>
+__global__ void k_fields(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf,
+                         double* __restrict__ ra, double* __restrict__ rb,
+                         double* __restrict__ ux, double* __restrict__ uy)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const S* f = (const S*)(base + d.off_f[buf]);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        const S* in = f + (long long)y * d.pitch + x;
+        double rho[2] = {0, 0}, jx = 0, jy = 0;
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 9; ++i) {
+                const double v = decode<P>(in + (9 * s + i) * d.plane, d, 9 * s + i);
+                rho[s] += v;
+                jx += v * CX[i];
+                jy += v * CY[i];
+            }
+        if (ra) ra[k] = rho[0];
+        if (rb) rb[k] = rho[1];
+        if (ux) ux[k] = jx / (rho[0] + rho[1]);
+        if (uy) uy[k] = jy / (rho[0] + rho[1]);
+    }
+}
+
+template <class P>
+__global__ void k_export(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, int q,
+                         double* __restrict__ out)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const S* f = (const S*)(base + d.off_f[buf]);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        out[k] = decode<P>(f + (long long)y * d.pitch + x + q * d.plane, d, q);
+    }
+}
+
+constexpr int RED_THREADS = 256;
+
+// Per-block FP64 partial sums of rho_A, rho_B, j_x, j_y and of the count of
+// sites whose density is non-finite or non-positive.
+template <class P>
+__global__ void __launch_bounds__(RED_THREADS)
+k_sums(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, double* __restrict__ partials)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const S* f = (const S*)(base + d.off_f[buf]);
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        const S* in = f + (long long)y * d.pitch + x;
+        double rho[2] = {0, 0};
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 9; ++i) {
+                const double v = decode<P>(in + (9 * s + i) * d.plane, d, 9 * s + i);
+                rho[s] += v;
+                acc[2] += v * CX[i];
+                acc[3] += v * CY[i];
+            }
+        acc[0] += rho[0];
+        acc[1] += rho[1];
+        const bool ok = (rho[0] > 0.0) && (rho[1] > 0.0) && (rho[0] < 1e300) && (rho[1] < 1e300);
+        if (!ok) acc[4] += 1.0;
+    }
+    __shared__ double red[RED_THREADS / 64][5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) acc[m] = wave_sum(acc[m]);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int m = 0; m < 5; ++m) red[wave][m] = acc[m];
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double t = 0;
+        for (int wv = 0; wv < RED_THREADS / 64; ++wv) t += red[wv][threadIdx.x];
+        partials[blockIdx.x * 5 + threadIdx.x] = t;
+    }
+}
+
+// Sums nparts partial rows of 5 in a fixed order into out[5]; sets *flag if
+// the bad-site count is non-zero (the flag is never cleared here).
+__global__ void __launch_bounds__(64)
+k_sums_final(const double* __restrict__ partials, int nparts, double* __restrict__ out,
+             int* __restrict__ flag)
+{
+    const int t = threadIdx.x;
+    if (t < 5) {
+        double s = 0;
+        for (int b = 0; b < nparts; ++b) s += partials[b * 5 + t];
+        out[t] = s;
+        if (t == 4 && s > 0.0 && flag) *flag = 1;
+    }
+}
+
+// Per lattice k: out[2k] = sum_x bottom accumulator, out[2k+1] = sum_x top.
+__global__ void __launch_bounds__(256)
+k_stress_reduce(char* __restrict__ base, const LatDesc* __restrict__ descs, double* __restrict__ out)
+{
+    const LatDesc& d = descs[blockIdx.x];
+    const double* st = (const double*)(base + d.off_stress);
+    __shared__ double red[4][2];
+    double a = 0, b = 0;
+    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
+        a += st[x];
+        b += st[d.nx + x];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[wave][0] = a; red[wave][1] = b; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0;
+        for (int wv = 0; wv < 4; ++wv) s += red[wv][threadIdx.x];
+        out[2 * blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+// out[y] = sum over the 64-column groups of the profile accumulator.
+__global__ void k_profile_reduce(char* __restrict__ base, const LatDesc* __restrict__ dd,
+                                 double* __restrict__ out)
+{
+    const LatDesc& d = *dd;
+    const double* pr = (const double*)(base + d.off_prof);
+    for (int y = blockIdx.x * blockDim.x + threadIdx.x; y < d.ny; y += gridDim.x * blockDim.x) {
+        double s = 0;
+        for (int g = 0; g < d.ngroups; ++g) s += pr[(long long)g * d.ny + y];
+        out[y] = s;
+    }
+}
+
+__global__ void k_fill(double* __restrict__ p, long long n, double v)
+{
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+// ---------------------------------------------------------- host launchers --
+
+template <int BX, class P>
+static hipError_t step_bx(char* base, const LatDesc* descs, int nlat, int ntot, int src, int grid,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step<BX, P>), dim3(grid), dim3(BX), 0, s, base, descs, nlat, ntot, src);
+    return hipGetLastError();
+}
+
+template <class P>
+static hipError_t step_p(int bx, char* base, const LatDesc* descs, int nlat, int ntot, int src,
+                         int grid, hipStream_t s)
+{
+    switch (bx) {
+    case 64: return step_bx<64, P>(base, descs, nlat, ntot, src, grid, s);
+    case 128: return step_bx<128, P>(base, descs, nlat, ntot, src, grid, s);
+    case 256: return step_bx<256, P>(base, descs, nlat, ntot, src, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+#define LBK_DISPATCH(storage, CALL)                                  \
+    switch (storage) {                                               \
+    case 0: { using P = StF64; return CALL; }                        \
+    case 1: { using P = StF32; return CALL; }                        \
+    case 2: { using P = StF16; return CALL; }                        \
+    case 3: { using P = StBF16; return CALL; }                       \
+    default: return hipErrorInvalidValue;                            \
+    }
+
+hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, int nlat, int ntot,
+                       int src, int grid, hipStream_t s)
+{
+    LBK_DISPATCH(storage, (step_p<P>(bx, base, descs, nlat, ntot, src, grid, s)));
+}
+
+static int grid_for(long long n, int threads)
+{
+    long long g = (n + threads - 1) / threads;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+template <class P>
+static hipError_t init_p(char* base, const LatDesc* d, long long n, int buf, const double* ra,
+                         const double* rb, const double* ux, const double* uy, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init<P>), dim3(grid_for(n, 256)), dim3(256), 0, s, base, d, buf, ra, rb, ux, uy);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+                       const double* ra, const double* rb, const double* ux, const double* uy,
+                       hipStream_t s)
+{
+    LBK_DISPATCH(storage, (init_p<P>(base, d, nsites, buf, ra, rb, ux, uy, s)));
+}
+
+template <class P>
+static hipError_t fields_p(char* base, const LatDesc* d, long long n, int buf, double* ra,
+                           double* rb, double* ux, double* uy, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fields<P>), dim3(grid_for(n, 256)), dim3(256), 0, s, base, d, buf, ra, rb, ux, uy);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+                         double* ra, double* rb, double* ux, double* uy, hipStream_t s)
+{
+    LBK_DISPATCH(storage, (fields_p<P>(base, d, nsites, buf, ra, rb, ux, uy, s)));
+}
+
+template <class P>
+static hipError_t export_p(char* base, const LatDesc* d, long long n, int buf, int q, double* out,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((k_export<P>), dim3(grid_for(n, 256)), dim3(256), 0, s, base, d, buf, q, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+                         int q, double* out, hipStream_t s)
+{
+    LBK_DISPATCH(storage, (export_p<P>(base, d, nsites, buf, q, out, s)));
+}
+
+template <class P>
+static hipError_t sums_p(char* base, const LatDesc* d, int buf, int nblocks, double* partials,
+                         double* out, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sums<P>), dim3(nblocks), dim3(RED_THREADS), 0, s, base, d, buf, partials);
+    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, s, partials, nblocks, out, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int nblocks,
+                       double* partials, double* out, int* flag, hipStream_t s)
+{
+    LBK_DISPATCH(storage, (sums_p<P>(base, d, buf, nblocks, partials, out, flag, s)));
+}
+
+hipError_t launch_stress_reduce(char* base, const LatDesc* descs, int nlat, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stress_reduce, dim3(nlat), dim3(256), 0, s, base, descs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_reduce(char* base, const LatDesc* d, int ny, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_profile_reduce, dim3(grid_for(ny, 256)), dim3(256), 0, s, base, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+int sums_blocks() { return 1024; }
+
+}  // namespace lbk

@@ -1,0 +1,26 @@
+// Host-side launchers of the library's kernels (internal to the HIP library).
+// `base` is the start of the caller's device state; descriptors hold byte
+// offsets from it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "lb_device.hpp"
+
+namespace lbk {
+
+hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, int nlat, int ntot,
+                       int src, int grid, hipStream_t s);
+hipError_t launch_init(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+                       const double* ra, const double* rb, const double* ux, const double* uy,
+                       hipStream_t s);
+hipError_t launch_fields(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+                         double* ra, double* rb, double* ux, double* uy, hipStream_t s);
+hipError_t launch_export(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+                         int q, double* out, hipStream_t s);
+hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int nblocks,
+                       double* partials, double* out, int* flag, hipStream_t s);
+hipError_t launch_stress_reduce(char* base, const LatDesc* descs, int nlat, double* out, hipStream_t s);
+hipError_t launch_profile_reduce(char* base, const LatDesc* d, int ny, double* out, hipStream_t s);
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
+int sums_blocks();
+
+}  // namespace lbk

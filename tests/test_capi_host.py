@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI that need no GPU: the built library loads,
+exports every function include/lb.h declares, and validates parameters before
+any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lb.h", "mlp.h")]
+
+
+def _declared(path):
+    if not os.path.exists(path):
+        return []
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:lb_status|const char\*|int32_t|void)\s+\**(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared(HEADERS[0])
+    for n in ("lb_init", "lb_step", "lb_fields", "lb_stress", "lb_state_bytes", "lb_destroy",
+              "lbb_init", "lbb_step", "lbb_stress"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1004_5058_amd import lb
+    L = lb.load_library()
+    missing = [n for h in HEADERS for n in _declared(h) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library the binding raises instead of falling back."""
+    from paper_1004_5058_amd import lb
+    saved = lb._lib
+    lb._lib = None
+    try:
+        with pytest.raises(ImportError):
+            lb.load_library(str(tmp_path / "missing.so"))
+    finally:
+        lb._lib = saved
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(rho0=0.0), "rho0"),
+    (dict(g_ab=float("inf")), "non-finite"),
+    (dict(storage=7), "storage"),
+])
+def test_state_bytes_rejects_bad_parameters(kw, msg):
+    from paper_1004_5058_amd import lb
+    p = lb.make_params(64, 64, **{k: v for k, v in kw.items() if k != "storage"})
+    if "storage" in kw:
+        p.storage = kw["storage"]
+    with pytest.raises(lb.LBError) as e:
+        lb.lb_state_bytes(p)
+    assert e.value.code == -1 and msg in str(e.value)
+
+
+def test_state_bytes_rejects_bad_sizes():
+    from paper_1004_5058_amd import lb
+    for nx, ny in [(0, 8), (8, 1), (70000, 8)]:
+        with pytest.raises(lb.LBError):
+            lb.lb_state_bytes(lb.make_params(nx, ny))
+    # one species' planes above 4 GiB of 32-bit buffer offsets
+    with pytest.raises(lb.LBError):
+        lb.lb_state_bytes(lb.make_params(16384, 16384, storage="f64"))
+
+
+def test_state_bytes_layout_scales_with_storage():
+    from paper_1004_5058_amd import lb
+    b64 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f64"))
+    b32 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f32"))
+    b16 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f16dev"))
+    pop = 2 * 18 * 512 * 256
+    assert b64 - b32 == pop * 4 and b32 - b16 == pop * 2
+
+
+def test_init_rejects_bad_inputs_before_device_work():
+    """Non-positive or non-finite initial densities and a misaligned or small
+    state are refused with LB_EINVAL / LB_ENOMEM without touching a GPU."""
+    from paper_1004_5058_amd import lb
+    L = lb.load_library()
+    p = lb.make_params(8, 8)
+    ra = np.full((8, 8), 0.5)
+    rb = np.full((8, 8), 0.5)
+    h = ctypes.c_void_p()
+    need = lb.lb_state_bytes(p)
+    fake = ctypes.c_void_p(4096)   # never dereferenced: validation fails first
+    bad = ra.copy()
+    bad[3, 4] = -0.1
+    assert L.lb_init(ctypes.byref(p), fake, need, None, lb._dptr(bad), lb._dptr(rb), None, None,
+                     ctypes.byref(h)) == -1
+    bad[3, 4] = float("nan")
+    assert L.lb_init(ctypes.byref(p), fake, need, None, lb._dptr(bad), lb._dptr(rb), None, None,
+                     ctypes.byref(h)) == -1
+    assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(4097), need, None, lb._dptr(ra), lb._dptr(rb),
+                     None, None, ctypes.byref(h)) == -1
+    assert L.lb_init(ctypes.byref(p), fake, need - 256, None, lb._dptr(ra), lb._dptr(rb), None, None,
+                     ctypes.byref(h)) == -2
+    assert b"smaller" in L.lb_last_error()
+    assert L.lb_step(None, 1) == -1
