@@ -1,0 +1,169 @@
+"""Benchmark of the two-species multirange lattice Boltzmann step on one MI355X.
+
+Workload: a 4096 x 4096 lattice, moving bounce-back walls at +-0.02 (Couette
+shear), random 50/50 emulsion start (rho 1.0 / 0.1 per site, seed 1) with the
+linear Couette velocity, symmetric couplings G^a = -9.0, G^r = 8.1 (both
+species), G_AB = 0.405, rho0 = 0.83, tau = 1.  A step is one full time step of
+both species: pseudo-potential, belt-1/two-belt forces, BGK collision,
+streaming, walls and the FP64 wall-stress accumulation.  Populations are FP32
+(headline `value`); FP16- and BF16-deviation storage are timed beside it.
+
+Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
+step (18 population loads + 18 stores per site) divided by the step kernel's
+average duration, timed with HIP events on the lattice's stream.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       [--variants f32,f16dev,bf16dev] [--size 4096]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72, "bf16dev": 72}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("lb_kernels.hip", "lb_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1004_5058_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per step from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(f"{workload}/{storage}")
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_step")
+
+
+def gpu_run(storage, n, steps, warmup, u=0.02, seed=1):
+    import torch
+    from paper_1004_5058_amd import inputs, lb
+    ra, rb = inputs.emulsion(n, n, seed=seed)
+    ux, uy = inputs.couette(n, n, u, -u)
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=storage, profile=False,
+                     **inputs.COUPLINGS)
+    del ra, rb, ux, uy
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # device time per step kernel, HIP events on the lattice's stream
+    ms_kernel = lat.time_steps(max(steps // 2, 1))
+    sb, st, ns = lat.stress()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    lups = float(n) * n
+    return dict(ms_per_step=1e3 * wall / steps, mlups=lups * steps / wall / 1e6,
+                ms_kernel=ms_kernel, stress=[sb, st], nsamples=ns)
+
+
+def cpu_baseline(n, steps=3, u=0.02, seed=1):
+    """The FP64 oracle on the same 4096^2 workload, a bounded number of steps."""
+    from oracle import oracle as O
+    from paper_1004_5058_amd import inputs
+    ra, rb = inputs.emulsion(n, n, seed=seed)
+    ux, uy = inputs.couette(n, n, u, -u)
+    p = O.OracleParams(nx=n, ny=n, walls=True, u_top=u, u_bot=-u, **inputs.COUPLINGS)
+    f = O.init(p, ra, rb, ux, uy)
+    del ra, rb, ux, uy
+    t0 = time.perf_counter()
+    f, _, _ = O.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=round(float(n) * n * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{steps} FP64 oracle steps of the full {n}x{n} lattice ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--variants", default="f32,f16dev,bf16dev")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported. "
+              "The path's sharding plan (y-slabs with halo rows, or whole lattices per GPU) "
+              "is described in the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if a.calib_copy:
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+    n = a.size
+    workload = f"couette_emulsion_{n}x{n}"
+    variants = [v for v in a.variants.split(",") if v]
+    res = {}
+    for v in variants:
+        res[v] = gpu_run(v, n, a.steps, a.warmup)
+        print(f"# {v}: {res[v]['mlups']:.0f} MLUPS, kernel {res[v]['ms_kernel']:.4f} ms/step", file=sys.stderr,
+              flush=True)
+    head = variants[0]
+    r = res[head]
+    bytes_step = BYTES_PER_LUP[head] * float(n) * n
+    achieved = bytes_step / (r["ms_kernel"] * 1e-3) / 1e9
+    traffic = measured_traffic(workload, head)
+    line = {
+        "metric": "MLUPS (2-species)",
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "f32" else head,
+        "data": "synthetic (seeded emulsion start, linear Couette velocity)",
+        "config": {"workload": workload, "nx": n, "ny": n, "storage": head, "walls": "bounce-back +-0.02",
+                   "tau": 1.0, "rho0": 0.83, "G": [-9.0, 8.1, -9.0, 8.1, 0.405]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "variants": {v: {"mlups": round(res[v]["mlups"], 1), "ms_kernel": round(res[v]["ms_kernel"], 5),
+                         "alg_gbs": round(BYTES_PER_LUP[v] * float(n) * n / (res[v]["ms_kernel"] * 1e-3) / 1e9, 1),
+                         "bytes_per_lup": BYTES_PER_LUP[v]} for v in variants},
+    }
+    for v in variants:
+        line["variants"][v]["frac"] = round(line["variants"][v]["alg_gbs"] / HBM_PEAK_GBS, 4)
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -219,7 +219,7 @@ lb_status decompose(lbb_handle* h)
         const Lat& a = h->lats[k];
         lbk::LatDesc& d = h->descs[k];
         d.nstrip = (a.p.nx + h->bx - 1) / h->bx;
-        d.ly = std::min(h->ly, a.p.ny);
+        d.ly = std::min(std::min(h->ly, a.p.ny), 256);   // the kernel's halo buffer holds 256 rows
         d.nseg = (a.p.ny + d.ly - 1) / d.ly;
         d.nitems = d.nstrip * d.nseg;
         item = (item + 7) / 8 * 8;

@@ -140,14 +140,35 @@ __device__ __forceinline__ int map_row(int r, int ny, int walls)
 
 // ------------------------------------------------------------------ step ---
 
+template <class C> struct V2;
+template <> struct V2<float> { using T = float2; };
+template <> struct V2<double> { using T = double2; };
+
+// Workgroup barrier that orders LDS only: global loads issued before it stay
+// in flight (the row prefetch), unlike __syncthreads().
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Largest segment (rows per tile) the halo buffer holds.
+constexpr int LY_MAX = 256;
+
 template <int BX, class P>
 __global__ void __launch_bounds__(BX)
 k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int ntot, int src)
 {
     using S = typename P::S;
     using C = typename P::C;
+    using C2 = typename V2<C>::T;
     using C4 = typename V4<C>::T;
-    __shared__ C4 ring[6][BX + 4];
+    // Six-row rings of (dpsi_A, dpsi_B) and (drho_A, drho_B); columns x0-2 .. x0+BX+1.
+    __shared__ C2 ringP[6][BX + 4];
+    __shared__ C2 ringR[6][BX + 4];
+    // The four halo columns of the whole segment (rows y0-2 .. y1+1).
+    __shared__ C4 halo[LY_MAX + 4][4];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -176,18 +197,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         const unsigned xc = x % (unsigned)nx;
         const unsigned xp = (xc + 1 == (unsigned)nx) ? 0u : xc + 1;
         const unsigned xm = (xc == 0) ? (unsigned)(nx - 1) : xc - 1;
-        unsigned hcol = 0;
-        int hidx = 0;
-        if (tid < 4) {
-            int hc = (tid < 2) ? x0 - 2 + tid : x0 + BX + tid - 2;
-            hc %= nx;
-            if (hc < 0) hc += nx;
-            hcol = (unsigned)hc;
-            hidx = (tid < 2) ? tid : BX + tid;
-        }
 
         const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
-        const C rho0 = coef<C>(d.rho0, d.frho0), inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
+        const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
         C ks0[5], ks1[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
@@ -207,42 +219,70 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         const rsrc_t rin0 = make_rsrc(fin, sbytes), rin1 = make_rsrc(fin + sbytes, sbytes);
         const rsrc_t rout0 = make_rsrc(fout, sbytes), rout1 = make_rsrc(fout + sbytes, sbytes);
         const int es = (int)sizeof(S);
-        const unsigned vc = xc * es, vp = xp * es, vm = xm * es, vh = hcol * es;
+        const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
         const int pbytes = (int)(plane * es), rbytes = pitch * es;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
 
-        // Load row r's populations into fr, stage (psi, rho) of row r in LDS.
-        auto stage = [&](C(&fr)[18], int r) {
-            const int rr = map_row<P>(r, ny, walls);
-            const int slot = (r - y0 + 2) % 6;
-            const int so = rr * rbytes;
+        // 18 deviations of row r (any row; mapped through the walls or the
+        // periodic wrap) at column byte offset voff.
+        auto load = [&](C(&fr)[18], int r, unsigned voff) {
+            const int so = map_row<P>(r, ny, walls) * rbytes;
 #pragma unroll
-            for (int q = 0; q < 18; ++q)
-                fr[q] = ld<P>(q < 9 ? rin0 : rin1, vc, so + (q % 9) * pbytes);
-            C ra = fr[0], rb = fr[9];
+            for (int q = 0; q < 18; ++q) fr[q] = ld<P>(q < 9 ? rin0 : rin1, voff, so + (q % 9) * pbytes);
+        };
+        auto dens = [&](const C(&fr)[18], C& da, C& db) {
+            da = fr[0];
+            db = fr[9];
 #pragma unroll
-            for (int q = 1; q < 9; ++q) { ra += fr[q]; rb += fr[9 + q]; }
-            C4 v;
-            v.x = dpsi_of(ra, e0, inv_rho0);
-            v.y = dpsi_of(rb, e1, inv_rho0);
-            v.z = ra;
-            v.w = rb;
-            ring[slot][tid + 2] = v;
-            if (tid < 4) {
+            for (int q = 1; q < 9; ++q) { da += fr[q]; db += fr[9 + q]; }
+        };
+
+        // Halo columns x0-2, x0-1, x0+BX, x0+BX+1 for every row of the segment.
+        {
+            const int nh = (y1 - y0 + 4) * 4;
+            for (int s = tid; s < nh; s += BX) {
+                const int c = s & 3, rr = s >> 2;
+                int hc = (c < 2) ? x0 - 2 + c : x0 + BX + c - 2;
+                hc %= nx;
+                if (hc < 0) hc += nx;
                 C h[18];
-#pragma unroll
-                for (int q = 0; q < 18; ++q)
-                    h[q] = ld<P>(q < 9 ? rin0 : rin1, vh, so + (q % 9) * pbytes);
-                C ha = h[0], hb = h[9];
-#pragma unroll
-                for (int q = 1; q < 9; ++q) { ha += h[q]; hb += h[9 + q]; }
-                C4 hv;
-                hv.x = dpsi_of(ha, e0, inv_rho0);
-                hv.y = dpsi_of(hb, e1, inv_rho0);
-                hv.z = ha;
-                hv.w = hb;
-                ring[slot][hidx] = hv;
+                load(h, y0 - 2 + rr, (unsigned)hc * es);
+                C da, db;
+                dens(h, da, db);
+                C4 v;
+                v.x = dpsi_of(da, e0, inv_rho0);
+                v.y = dpsi_of(db, e1, inv_rho0);
+                v.z = da;
+                v.w = db;
+                halo[rr][c] = v;
+            }
+        }
+        lds_barrier();
+
+        // Stage row r (populations already in fr): (dpsi, drho) into the ring,
+        // plus the four halo entries copied by lanes 0..3.
+        auto stage = [&](const C(&fr)[18], int r) {
+            const int slot = (r - y0 + 2) % 6;
+            C da, db;
+            dens(fr, da, db);
+            C2 pv, rv;
+            pv.x = dpsi_of(da, e0, inv_rho0);
+            pv.y = dpsi_of(db, e1, inv_rho0);
+            rv.x = da;
+            rv.y = db;
+            ringP[slot][tid + 2] = pv;
+            ringR[slot][tid + 2] = rv;
+            if (tid < 4) {
+                const C4 hv = halo[r - y0 + 2][tid];
+                const int hidx = (tid < 2) ? tid : BX + tid;
+                C2 a, b;
+                a.x = hv.x;
+                a.y = hv.y;
+                b.x = hv.z;
+                b.y = hv.w;
+                ringP[slot][hidx] = a;
+                ringR[slot][hidx] = b;
             }
         };
 
@@ -250,14 +290,14 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         auto collide = [&](const C(&f)[18], int y) {
             int sl[5];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sl[k] = (y - 2 + k - y0 + 2) % 6;
+            for (int k = 0; k < 5; ++k) sl[k] = (y + k - y0) % 6;
             C sxA = 0, syA = 0, sxB = 0, syB = 0, cxA = 0, cyA = 0, cxB = 0, cyB = 0;
 #pragma unroll
             for (int dy = -2; dy <= 2; ++dy) {
 #pragma unroll
                 for (int dx = -2; dx <= 2; ++dx) {
                     if (dx == 0 && dy == 0) continue;
-                    const C4 n = ring[sl[dy + 2]][tid + 2 + dx];
+                    const C2 n = ringP[sl[dy + 2]][tid + 2 + dx];
                     const int sh = shell_of(dx, dy);
                     if (dx != 0) {
                         sxA += (ks0[sh] * (C)dx) * n.x;
@@ -268,16 +308,19 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                         syB += (ks1[sh] * (C)dy) * n.y;
                     }
                     if (sh <= 1) {
+                        const C2 m = ringR[sl[dy + 2]][tid + 2 + dx];
                         const C kk = (sh == 0) ? kx1 : kx2;
-                        if (dx != 0) { cxA += (kk * (C)dx) * n.w; cxB += (kk * (C)dx) * n.z; }
-                        if (dy != 0) { cyA += (kk * (C)dy) * n.w; cyB += (kk * (C)dy) * n.z; }
+                        if (dx != 0) { cxA += (kk * (C)dx) * m.y; cxB += (kk * (C)dx) * m.x; }
+                        if (dy != 0) { cyA += (kk * (C)dy) * m.y; cyB += (kk * (C)dy) * m.x; }
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            const C4 c0 = ring[sl[2]][tid + 2];
+            const C2 p0 = ringP[sl[2]][tid + 2];
+            const C2 r0c = ringR[sl[2]][tid + 2];
             // absolute densities and potentials of the centre site
-            const C ra = rref0 + c0.z, rb = rref1 + c0.w;
-            const C pa = pref0 + c0.x, pb = pref1 + c0.y;
+            const C ra = rref0 + r0c.x, rb = rref1 + r0c.y;
+            const C pa = pref0 + p0.x, pb = pref1 + p0.y;
             const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
             const C FxB = -pb * sxB - rb * cxB, FyB = -pb * syB - rb * cyB;
 
@@ -311,8 +354,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
             };
-            relax(0, ra, c0.z, FxA, FyA);
-            relax(1, rb, c0.w, FxB, FyB);
+            relax(0, ra, r0c.x, FxA, FyA);
+            relax(1, rb, r0c.y, FxB, FyB);
 
             if (prof != nullptr && x0 + 64 * wave < nx) {    // wave-uniform condition
                 double s = valid ? (double)ux : 0.0;
@@ -353,25 +396,30 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
             if (top) stress[nx + xc] += (double)mom_t;
         };
 
-        C F0[18], F1[18], F2[18];
+        // Pipeline: entering iteration y, rows y and y+1 are staged and held,
+        // row y+2 is loaded (in flight); the iteration issues row y+3's loads,
+        // stages row y+2, waits on the LDS barrier and collides row y.
+        C F0[18], F1[18], F2[18], F3[18];
+        load(F2, y0 - 2, vc);
+        load(F3, y0 - 1, vc);
         stage(F2, y0 - 2);
-        stage(F2, y0 - 1);
+        stage(F3, y0 - 1);
+        load(F0, y0, vc);
+        load(F1, y0 + 1, vc);
+        load(F2, y0 + 2, vc);
         stage(F0, y0);
         stage(F1, y0 + 1);
-        for (int y = y0; y < y1; y += 3) {
-            stage(F2, y + 2);
-            __syncthreads();
-            collide(F0, y);
-            if (y + 1 < y1) {
-                stage(F0, y + 3);
-                __syncthreads();
-                collide(F1, y + 1);
-            }
-            if (y + 2 < y1) {
-                stage(F1, y + 4);
-                __syncthreads();
-                collide(F2, y + 2);
-            }
+        auto iter = [&](int y, const C(&fc)[18], const C(&fs2)[18], C(&fl)[18]) {
+            if (y + 3 <= y1 + 1) load(fl, y + 3, vc);
+            stage(fs2, y + 2);
+            lds_barrier();
+            collide(fc, y);
+        };
+        for (int y = y0; y < y1; y += 4) {
+            iter(y, F0, F2, F3);
+            if (y + 1 < y1) iter(y + 1, F1, F3, F0);
+            if (y + 2 < y1) iter(y + 2, F2, F0, F1);
+            if (y + 3 < y1) iter(y + 3, F3, F1, F2);
         }
         __syncthreads();
     }
