@@ -88,6 +88,7 @@ typedef struct {
 } lb_params;
 
 typedef struct lb_handle lb_handle;
+typedef struct lbb_handle lbb_handle;
 
 /* Device bytes a single lattice with these parameters needs. */
 lb_status lb_state_bytes(const lb_params* p, size_t* bytes);
@@ -156,6 +157,19 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
 lb_status lb_save(lb_handle* h, void* buf, size_t* bytes);
 lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
 
+/* Autotuner: times `steps` steps of every candidate launch shape (bx in
+ * {64, 128, 256}, ly in {16..256}; for batches also persistent grids of 1, 2
+ * and 4 blocks per compute unit) on this lattice, applies the fastest and
+ * restores the simulation state exactly (populations, accumulators, step
+ * count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid, ms}},
+ * key "<gfx arch>/<storage>/<nx>x<ny>" (batches: "batch<n>_<sites>"); a cached
+ * entry is applied without timing, a new result is added.  Synchronises.
+ * Allocates a temporary device copy of the state while timing. */
+lb_status lb_autotune(lb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
+                      double* ms);
+lb_status lbb_autotune(lbb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
+                       int32_t* grid, double* ms);
+
 /* Steps taken since init (or restored by lb_load). */
 lb_status lb_time(lb_handle* h, int64_t* t);
 
@@ -171,8 +185,6 @@ const char* lb_last_error(void);
  * of many steps).  All lattices share the storage precision of params[0].
  * Arrays of per-lattice host pointers follow the single-lattice rules.
  */
-typedef struct lbb_handle lbb_handle;
-
 lb_status lbb_state_bytes(const lb_params* params, int32_t n, size_t* bytes);
 lb_status lbb_init(const lb_params* params, int32_t n, void* dev_state, size_t bytes,
                    void* hip_stream, const double* const* rho_a, const double* const* rho_b,

@@ -173,6 +173,9 @@ void fill_desc(const Lat& a, lbk::LatDesc& d)
 
 }  // namespace
 
+// Shared with the surrogate network's C ABI: sets lb_last_error()'s message.
+void lbi_set_error(const char* msg) { g_err = msg; }
+
 // ---------------------------------------------------------------- the batch --
 
 struct lbb_handle {
@@ -188,6 +191,7 @@ struct lbb_handle {
     int64_t t = 0, nsamples = 0;
     int bx = 256, ly = 64, grid = 0; // grid 0: one block per tile
     int ntot = 0;
+    int ly_max = 1;                  // largest rows-per-tile over the lattices
     int graph_steps = 32;
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // graph starting from buffer 0 / 1
     int watchdog = 0;
@@ -215,12 +219,14 @@ void drop_graphs(lbb_handle* h)
 lb_status decompose(lbb_handle* h)
 {
     int item = 0;
+    h->ly_max = 1;
     for (size_t k = 0; k < h->lats.size(); ++k) {
         const Lat& a = h->lats[k];
         lbk::LatDesc& d = h->descs[k];
         d.nstrip = (a.p.nx + h->bx - 1) / h->bx;
         d.ly = std::min(std::min(h->ly, a.p.ny), 256);   // the kernel's halo buffer holds 256 rows
         d.nseg = (a.p.ny + d.ly - 1) / d.ly;
+        h->ly_max = std::max(h->ly_max, d.ly);
         d.nitems = d.nstrip * d.nseg;
         item = (item + 7) / 8 * 8;
         d.item_begin = item;
@@ -243,7 +249,7 @@ int launch_grid(const lbb_handle* h)
 lb_status launch_one(lbb_handle* h, hipStream_t s, int src)
 {
     hipError_t e = lbk::launch_step(h->storage, h->bx, h->base, h->d_desc(), (int)h->lats.size(),
-                                    h->ntot, src, launch_grid(h), s);
+                                    h->ntot, src, launch_grid(h), h->ly_max, s);
     if (e != hipSuccess) return fail(LB_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
     return LB_OK;
 }
@@ -489,6 +495,16 @@ lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
     return decompose(h);
 }
 
+lb_status steps_direct_warm(lbb_handle* h, int n)
+{
+    for (int k = 0; k < n; ++k) {
+        lb_status st = launch_one(h, h->stream, h->cur);
+        if (st != LB_OK) return st;
+        h->cur ^= 1;
+    }
+    return LB_OK;
+}
+
 lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
 {
     if (n < 1 || !ms) return fail(LB_EINVAL, "need n >= 1 and an output");
@@ -505,6 +521,186 @@ lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
     (void)hipEventDestroy(b);
     if (st != LB_OK) return st;
     *ms = (double)t / n;
+    return LB_OK;
+}
+
+// ------------------------------------------------------------- autotuner --
+//
+// Times the step kernel over candidate launch shapes on the handle's own
+// lattices, keeps the fastest and leaves the simulation state exactly as it
+// was (populations, accumulators and counters are copied aside on the device
+// and restored).  Results are cached in a small JSON file keyed by
+// "<arch>/<storage>/<lattice shape>".
+
+struct TuneEntry {
+    int bx = 0, ly = 0, grid = 0;
+    double ms = 0;
+};
+
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+const char* storage_name(int s)
+{
+    static const char* n[] = {"f64", "f32", "f16dev", "bf16dev"};
+    return (s >= 0 && s < 4) ? n[s] : "unknown";
+}
+
+std::string tune_key(const lbb_handle* h)
+{
+    char buf[160];
+    if (h->lats.size() == 1) {
+        snprintf(buf, sizeof buf, "%s/%s/%dx%d", arch_name().c_str(), storage_name(h->storage),
+                 h->lats[0].p.nx, h->lats[0].p.ny);
+    } else {
+        long long sites = 0;
+        for (const Lat& a : h->lats) sites += (long long)a.p.nx * a.p.ny;
+        snprintf(buf, sizeof buf, "%s/%s/batch%zu_%lld", arch_name().c_str(), storage_name(h->storage),
+                 h->lats.size(), sites);
+    }
+    return buf;
+}
+
+// Reads {"key": {"bx": .., "ly": .., "grid": .., "ms": ..}, ...} one entry per line.
+std::vector<std::pair<std::string, TuneEntry>> read_cache(const char* path)
+{
+    std::vector<std::pair<std::string, TuneEntry>> out;
+    FILE* f = path ? fopen(path, "r") : nullptr;
+    if (!f) return out;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        const char* q1 = strchr(line, '"');
+        const char* q2 = q1 ? strchr(q1 + 1, '"') : nullptr;
+        if (!q1 || !q2 || !strstr(q2, "{")) continue;
+        TuneEntry e;
+        const char* p;
+        if ((p = strstr(q2, "\"bx\":"))) e.bx = atoi(p + 5);
+        if ((p = strstr(q2, "\"ly\":"))) e.ly = atoi(p + 5);
+        if ((p = strstr(q2, "\"grid\":"))) e.grid = atoi(p + 7);
+        if ((p = strstr(q2, "\"ms\":"))) e.ms = strtod(p + 5, nullptr);
+        out.emplace_back(std::string(q1 + 1, q2 - q1 - 1), e);
+    }
+    fclose(f);
+    return out;
+}
+
+lb_status write_cache(const char* path, const std::vector<std::pair<std::string, TuneEntry>>& ents)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(LB_EINVAL, "cannot write tuning cache %s", path);
+    fprintf(f, "{\n");
+    for (size_t i = 0; i < ents.size(); ++i)
+        fprintf(f, "\"%s\": {\"bx\": %d, \"ly\": %d, \"grid\": %d, \"ms\": %.6f}%s\n", ents[i].first.c_str(),
+                ents[i].second.bx, ents[i].second.ly, ents[i].second.grid, ents[i].second.ms,
+                i + 1 < ents.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+    if (rename(tmp.c_str(), path) != 0) return fail(LB_EINVAL, "cannot replace tuning cache %s", path);
+    return LB_OK;
+}
+
+lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch, TuneEntry* best_out)
+{
+    if (steps < 1) return fail(LB_EINVAL, "need steps >= 1");
+    const std::string key = tune_key(h);
+    auto cache = read_cache(cache_path);
+    for (auto& kv : cache)
+        if (kv.first == key && kv.second.bx) {
+            lb_status st = set_launch(h, kv.second.bx, kv.second.ly, kv.second.grid);
+            if (st != LB_OK) return st;
+            if (best_out) *best_out = kv.second;
+            return LB_OK;
+        }
+    // save the state
+    size_t total = 0;
+    std::vector<size_t> fb(h->lats.size()), ab(h->lats.size());
+    for (size_t k = 0; k < h->lats.size(); ++k) {
+        const Lat& a = h->lats[k];
+        fb[k] = 18ull * a.plane * storage_size(h->storage);
+        ab[k] = a.end - a.off_stress;
+        total += fb[k] + ab[k];
+    }
+    char* save = nullptr;
+    HIP_TRY(hipMalloc(&save, total));
+    size_t o = 0;
+    for (size_t k = 0; k < h->lats.size(); ++k) {
+        const Lat& a = h->lats[k];
+        HIP_TRY(hipMemcpyAsync(save + o, h->base + a.off_f[h->cur], fb[k], hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(save + o + fb[k], h->base + a.off_stress, ab[k], hipMemcpyDeviceToDevice, h->stream));
+        o += fb[k] + ab[k];
+    }
+    const int cur = h->cur;
+    const int64_t t = h->t, ns = h->nsamples;
+    const int bx0 = h->bx, ly0 = h->ly, grid0 = h->grid, gs0 = h->graph_steps, wd0 = h->watchdog;
+    h->graph_steps = 0;
+    h->watchdog = 0;
+
+    int maxnx = 0, maxny = 0;
+    for (const Lat& a : h->lats) { maxnx = std::max(maxnx, a.p.nx); maxny = std::max(maxny, a.p.ny); }
+    int dev = 0, ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        ncu = prop.multiProcessorCount;
+    TuneEntry best;
+    lb_status st = LB_OK;
+    for (int bx : {64, 128, 256}) {
+        if (bx > 64 && bx / 2 >= maxnx) continue;
+        for (int ly : {16, 32, 64, 128, 256}) {
+            if (ly > 16 && ly / 2 >= maxny) continue;
+            std::vector<int> grids = {0};
+            if (batch)
+                for (int per : {1, 2, 4}) grids.push_back(ncu * per);
+            for (int grid : grids) {
+                st = set_launch(h, bx, ly, grid);
+                if (st != LB_OK) break;
+                st = steps_direct_warm(h, 2);
+                if (st != LB_OK) break;
+                double ms = 0;
+                st = time_steps(h, steps, &ms);
+                if (st != LB_OK) break;
+                if (!best.bx || ms < best.ms) { best.bx = bx; best.ly = ly; best.grid = grid; best.ms = ms; }
+            }
+            if (st != LB_OK) break;
+        }
+        if (st != LB_OK) break;
+    }
+    // restore the state
+    o = 0;
+    h->cur = cur;
+    for (size_t k = 0; k < h->lats.size(); ++k) {
+        const Lat& a = h->lats[k];
+        (void)hipMemcpyAsync(h->base + a.off_f[cur], save + o, fb[k], hipMemcpyDeviceToDevice, h->stream);
+        (void)hipMemcpyAsync(h->base + a.off_stress, save + o + fb[k], ab[k], hipMemcpyDeviceToDevice, h->stream);
+        o += fb[k] + ab[k];
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(save);
+    h->t = t;
+    h->nsamples = ns;
+    h->graph_steps = gs0;
+    h->watchdog = wd0;
+    if (st != LB_OK) {
+        (void)set_launch(h, bx0, ly0, grid0);
+        return st;
+    }
+    st = set_launch(h, best.bx, best.ly, best.grid);
+    if (st != LB_OK) return st;
+    if (best_out) *best_out = best;
+    if (cache_path) {
+        bool found = false;
+        for (auto& kv : cache)
+            if (kv.first == key) { kv.second = best; found = true; }
+        if (!found) cache.emplace_back(key, best);
+        return write_cache(cache_path, cache);
+    }
     return LB_OK;
 }
 
@@ -741,6 +937,18 @@ lb_status lb_time_steps(lb_handle* h, int32_t n, double* ms)
     return time_steps(&h->b, n, ms);
 }
 
+lb_status lb_autotune(lb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly, double* ms)
+{
+    CHECK_H(h);
+    TuneEntry e;
+    lb_status st = autotune(&h->b, cache_path, steps, false, &e);
+    if (st != LB_OK) return st;
+    if (bx) *bx = e.bx;
+    if (ly) *ly = e.ly;
+    if (ms) *ms = e.ms;
+    return LB_OK;
+}
+
 lb_status lb_destroy(lb_handle* h)
 {
     if (!h) return LB_OK;
@@ -810,6 +1018,20 @@ lb_status lbb_time_steps(lbb_handle* h, int32_t n, double* ms)
 {
     CHECK_H(h);
     return time_steps(h, n, ms);
+}
+
+lb_status lbb_autotune(lbb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
+                       int32_t* grid, double* ms)
+{
+    CHECK_H(h);
+    TuneEntry e;
+    lb_status st = autotune(h, cache_path, steps, true, &e);
+    if (st != LB_OK) return st;
+    if (bx) *bx = e.bx;
+    if (ly) *ly = e.ly;
+    if (grid) *grid = e.grid;
+    if (ms) *ms = e.ms;
+    return LB_OK;
 }
 
 lb_status lbb_destroy(lbb_handle* h)

@@ -90,18 +90,56 @@ template <> __device__ __forceinline__ void bstore<__bf16>(__bf16 v, rsrc_t r, u
 }
 
 // Load / store one deviation, converting between the storage and the
-// arithmetic type (round to nearest even on the way down).
+// arithmetic type (round to nearest even on the way down).  The SGPR offset is
+// uniform by construction; readfirstlane states it, so a store under a
+// divergent branch does not become a per-lane loop.
 template <class P>
 __device__ __forceinline__ typename P::C ld(rsrc_t r, unsigned voff, int soff)
 {
-    return (typename P::C)bload<typename P::S>(r, voff, soff);
+    return (typename P::C)bload<typename P::S>(r, voff, __builtin_amdgcn_readfirstlane(soff));
 }
 
 template <class P>
 __device__ __forceinline__ void st(rsrc_t r, unsigned voff, int soff, typename P::C v)
 {
-    bstore<typename P::S>((typename P::S)v, r, voff, soff);
+    bstore<typename P::S>((typename P::S)v, r, voff, __builtin_amdgcn_readfirstlane(soff));
 }
+
+// The 18 populations of one site held in registers between the row load and
+// the collision: the arithmetic type for 32/64-bit storage; for 16-bit storage
+// the raw values, two per VGPR (d16 loads fill the low and high halves), and
+// converted when read.
+template <class P, bool PACK = (sizeof(typename P::S) == 2)> struct Row;
+
+template <class P> struct Row<P, false> {
+    using C = typename P::C;
+    C v[18];
+    __device__ __forceinline__ C operator[](int q) const { return v[q]; }
+    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned voff, int so, int pbytes)
+    {
+#pragma unroll
+        for (int q = 0; q < 18; ++q) v[q] = ld<P>(q < 9 ? r0 : r1, voff, so + (q % 9) * pbytes);
+    }
+};
+
+template <class P> struct Row<P, true> {
+    using S = typename P::S;
+    typedef S S2 __attribute__((ext_vector_type(2)));
+    S2 v[9];
+    __device__ __forceinline__ float operator[](int q) const
+    {
+        return (float)((q & 1) ? v[q >> 1].y : v[q >> 1].x);
+    }
+    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned voff, int so, int pbytes)
+    {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int q0 = 2 * k, q1 = 2 * k + 1;
+            v[k].x = bload<S>(q0 < 9 ? r0 : r1, voff, __builtin_amdgcn_readfirstlane(so + (q0 % 9) * pbytes));
+            v[k].y = bload<S>(q1 < 9 ? r0 : r1, voff, __builtin_amdgcn_readfirstlane(so + (q1 % 9) * pbytes));
+        }
+    }
+};
 
 // Deviation of the pseudo-potential from its value at the reference density:
 // psi(rho_ref + d) - psi(rho_ref) = -E expm1(-d/rho0), E = rho0 exp(-rho_ref/rho0).
@@ -153,8 +191,16 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Largest segment (rows per tile) the halo buffer holds.
+// Largest segment (rows per tile).
 constexpr int LY_MAX = 256;
+
+// Dynamic LDS of the step kernel: the four halo columns of a segment
+// (rows y0-2 .. y1+1) and the per-wave row sums of u_x for the profile.
+template <class C>
+__host__ __device__ constexpr size_t step_dyn_lds(int bx, int ly)
+{
+    return sizeof(C) * 4 * 4 * (size_t)(ly + 4) + sizeof(double) * (size_t)(bx / 64) * ly;
+}
 
 template <int BX, class P>
 __global__ void __launch_bounds__(BX)
@@ -167,8 +213,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
     // Six-row rings of (dpsi_A, dpsi_B) and (drho_A, drho_B); columns x0-2 .. x0+BX+1.
     __shared__ C2 ringP[6][BX + 4];
     __shared__ C2 ringR[6][BX + 4];
-    // The four halo columns of the whole segment (rows y0-2 .. y1+1).
-    __shared__ C4 halo[LY_MAX + 4][4];
+    extern __shared__ __align__(16) char dyn_lds[];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -223,15 +268,17 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         const int pbytes = (int)(plane * es), rbytes = pitch * es;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
+        C4* halo = (C4*)dyn_lds;                                       // [(ly + 4) * 4]
+        double* profS = (double*)(dyn_lds + sizeof(C4) * 4 * (d.ly + 4)); // [BX/64][ly]
+        C mom_b = 0, mom_t = 0;   // wall momentum of this thread's column, summed over the segment
 
         // 18 deviations of row r (any row; mapped through the walls or the
         // periodic wrap) at column byte offset voff.
-        auto load = [&](C(&fr)[18], int r, unsigned voff) {
-            const int so = map_row<P>(r, ny, walls) * rbytes;
-#pragma unroll
-            for (int q = 0; q < 18; ++q) fr[q] = ld<P>(q < 9 ? rin0 : rin1, voff, so + (q % 9) * pbytes);
+        using R = Row<P>;
+        auto load = [&](R& fr, int r, unsigned voff) {
+            fr.load(rin0, rin1, voff, map_row<P>(r, ny, walls) * rbytes, pbytes);
         };
-        auto dens = [&](const C(&fr)[18], C& da, C& db) {
+        auto dens = [&](const R& fr, C& da, C& db) {
             da = fr[0];
             db = fr[9];
 #pragma unroll
@@ -246,7 +293,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 int hc = (c < 2) ? x0 - 2 + c : x0 + BX + c - 2;
                 hc %= nx;
                 if (hc < 0) hc += nx;
-                C h[18];
+                R h;
                 load(h, y0 - 2 + rr, (unsigned)hc * es);
                 C da, db;
                 dens(h, da, db);
@@ -255,14 +302,14 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 v.y = dpsi_of(db, e1, inv_rho0);
                 v.z = da;
                 v.w = db;
-                halo[rr][c] = v;
+                halo[rr * 4 + c] = v;
             }
         }
         lds_barrier();
 
         // Stage row r (populations already in fr): (dpsi, drho) into the ring,
         // plus the four halo entries copied by lanes 0..3.
-        auto stage = [&](const C(&fr)[18], int r) {
+        auto stage = [&](const R& fr, int r) {
             const int slot = (r - y0 + 2) % 6;
             C da, db;
             dens(fr, da, db);
@@ -274,7 +321,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
             ringP[slot][tid + 2] = pv;
             ringR[slot][tid + 2] = rv;
             if (tid < 4) {
-                const C4 hv = halo[r - y0 + 2][tid];
+                const C4 hv = halo[(r - y0 + 2) * 4 + tid];
                 const int hidx = (tid < 2) ? tid : BX + tid;
                 C2 a, b;
                 a.x = hv.x;
@@ -287,7 +334,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         };
 
         // Collide row y (populations in f, neighbourhood in LDS) and push.
-        auto collide = [&](const C(&f)[18], int y) {
+        auto collide = [&](const R& f, int y) {
             int sl[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) sl[k] = (y + k - y0) % 6;
@@ -314,7 +361,10 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                         if (dy != 0) { cyA += (kk * (C)dy) * m.y; cyB += (kk * (C)dy) * m.x; }
                     }
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                // Keep the LDS reads of one stencil row next to their FMAs (bounds
+                // the registers the neighbourhood occupies).
+                asm volatile("" : "+v"(sxA), "+v"(syA), "+v"(sxB), "+v"(syB), "+v"(cxA), "+v"(cyA),
+                             "+v"(cxB), "+v"(cyB)::"memory");
             }
             const C2 p0 = ringP[sl[2]][tid + 2];
             const C2 r0c = ringR[sl[2]][tid + 2];
@@ -331,10 +381,18 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
             const C inv_rho = rcp(ra + rb);
             const C ux = jx * inv_rho, uy = jy * inv_rho;
 
-            C fs[18];
+            if (prof != nullptr && x0 + 64 * wave < nx) {    // wave-uniform condition
+                double su = valid ? (double)ux : 0.0;
+                su = wave_sum(su);
+                if ((tid & 63) == 0) profS[wave * d.ly + (y - y0)] = su;
+            }
+
+            const bool bot = walls && (y == 0);
+            const bool top = walls && (y == ny - 1);
             // BGK relaxation of the deviations towards
-            // f^eq_i - w_i rho_ref = w_i [drho + rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)]
-            auto relax = [&](int s, C rs, C drs, C Fx, C Fy) {
+            // f^eq_i - w_i rho_ref = w_i [drho + rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)],
+            // then the push of species s to the neighbours (bounce-back at walls).
+            auto relax_push = [&](int s, C rs, C drs, C Fx, C Fy) {
                 const C inv = rcp(rs);
                 const C vx = ux + tau * Fx * inv;
                 const C vy = uy + tau * Fy * inv;
@@ -342,64 +400,48 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 const C r0 = rs * (C)(4.0 / 9.0), r1 = rs * (C)(1.0 / 9.0), r2 = rs * (C)(1.0 / 36.0);
                 const C d1 = drs * (C)(1.0 / 9.0), d2 = drs * (C)(1.0 / 36.0);
                 const int o = 9 * s;
-                fs[o + 0] = f[o + 0] - omega * (f[o + 0] - (drs * (C)(4.0 / 9.0) - r0 * usq));
+                C fs[9];
+                fs[0] = f[o + 0] - omega * (f[o + 0] - (drs * (C)(4.0 / 9.0) - r0 * usq));
                 auto pair = [&](int ip, int im, C rw, C dw, C cu) {
                     const C sym = dw + rw * ((C)4.5 * cu * cu - usq);
                     const C anti = rw * ((C)3 * cu);
-                    fs[o + ip] = f[o + ip] - omega * (f[o + ip] - (sym + anti));
-                    fs[o + im] = f[o + im] - omega * (f[o + im] - (sym - anti));
+                    fs[ip] = f[o + ip] - omega * (f[o + ip] - (sym + anti));
+                    fs[im] = f[o + im] - omega * (f[o + im] - (sym - anti));
                 };
                 pair(1, 3, r1, d1, vx);
                 pair(2, 4, r1, d1, vy);
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
-            };
-            relax(0, ra, r0c.x, FxA, FyA);
-            relax(1, rb, r0c.y, FxB, FyB);
-
-            if (prof != nullptr && x0 + 64 * wave < nx) {    // wave-uniform condition
-                double s = valid ? (double)ux : 0.0;
-                s = wave_sum(s);
-                if ((tid & 63) == 0) {
-                    double* pp = prof + (long long)(x0 / 64 + wave) * ny + y;
-                    *pp += s;
-                }
-            }
-            if (!valid) return;
-
-            const bool bot = walls && (y == 0);
-            const bool top = walls && (y == ny - 1);
-            C mom_b = 0, mom_t = 0;
-#pragma unroll
-            for (int q = 0; q < 18; ++q) {
-                const int s = q / 9, i = q % 9;
-                const int cx = CX[i], cy = CY[i];
-                const C rs = (s == 0) ? ra : rb;
+                if (!valid) return;
                 const rsrc_t ro = (s == 0) ? rout0 : rout1;
-                if (cy < 0 && bot) {
-                    const C back = (cx != 0) ? fs[q] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[q];
-                    st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
-                    if (cx != 0) mom_b += (C)cx * (fs[q] + back);
-                } else if (cy > 0 && top) {
-                    const C back = (cx != 0) ? fs[q] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[q];
-                    st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
-                    if (cx != 0) mom_t += (C)cx * (fs[q] + back);
-                } else {
-                    int yt = y + cy;
-                    if (yt < 0) yt += ny;
-                    else if (yt >= ny) yt -= ny;
-                    const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
-                    st<P>(ro, vcol, i * pbytes + yt * rbytes, fs[q]);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int cx = CX[i], cy = CY[i];
+                    if (cy < 0 && bot) {
+                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
+                        st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
+                        if (cx != 0) mom_b += (C)cx * (fs[i] + back);
+                    } else if (cy > 0 && top) {
+                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
+                        st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
+                        if (cx != 0) mom_t += (C)cx * (fs[i] + back);
+                    } else {
+                        int yt = y + cy;
+                        if (yt < 0) yt += ny;
+                        else if (yt >= ny) yt -= ny;
+                        const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
+                        st<P>(ro, vcol, i * pbytes + yt * rbytes, fs[i]);
+                    }
                 }
-            }
-            if (bot) stress[xc] += (double)mom_b;
-            if (top) stress[nx + xc] += (double)mom_t;
+            };
+            relax_push(0, ra, r0c.x, FxA, FyA);
+            relax_push(1, rb, r0c.y, FxB, FyB);
         };
 
         // Pipeline: entering iteration y, rows y and y+1 are staged and held,
         // row y+2 is loaded (in flight); the iteration issues row y+3's loads,
         // stages row y+2, waits on the LDS barrier and collides row y.
-        C F0[18], F1[18], F2[18], F3[18];
+        R F0, F1, F2, F3;
         load(F2, y0 - 2, vc);
         load(F3, y0 - 1, vc);
         stage(F2, y0 - 2);
@@ -409,7 +451,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         load(F2, y0 + 2, vc);
         stage(F0, y0);
         stage(F1, y0 + 1);
-        auto iter = [&](int y, const C(&fc)[18], const C(&fs2)[18], C(&fl)[18]) {
+        auto iter = [&](int y, const R& fc, const R& fs2, R& fl) {
             if (y + 3 <= y1 + 1) load(fl, y + 3, vc);
             stage(fs2, y + 2);
             lds_barrier();
@@ -420,6 +462,18 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
             if (y + 1 < y1) iter(y + 1, F1, F3, F0);
             if (y + 2 < y1) iter(y + 2, F2, F0, F1);
             if (y + 3 < y1) iter(y + 3, F3, F1, F2);
+        }
+        // FP64 accumulators, once per tile: wall momentum of the boundary rows
+        // and the per-64-column row sums of u_x.
+        if (valid && walls && y0 == 0) stress[xc] += (double)mom_b;
+        if (valid && walls && y1 == ny) stress[nx + xc] += (double)mom_t;
+        __syncthreads();
+        if (prof != nullptr) {
+            const int nr = y1 - y0;
+            for (int e = tid; e < (BX / 64) * nr; e += BX) {
+                const int wv = e / nr, r = e % nr;
+                if (x0 + 64 * wv < nx) prof[(long long)(x0 / 64 + wv) * ny + y0 + r] += profS[wv * d.ly + r];
+            }
         }
         __syncthreads();
     }
@@ -614,20 +668,21 @@ __global__ void k_fill(double* __restrict__ p, long long n, double v)
 
 template <int BX, class P>
 static hipError_t step_bx(char* base, const LatDesc* descs, int nlat, int ntot, int src, int grid,
-                          hipStream_t s)
+                          int ly, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<BX, P>), dim3(grid), dim3(BX), 0, s, base, descs, nlat, ntot, src);
+    const size_t dyn = step_dyn_lds<typename P::C>(BX, ly);
+    hipLaunchKernelGGL((k_step<BX, P>), dim3(grid), dim3(BX), dyn, s, base, descs, nlat, ntot, src);
     return hipGetLastError();
 }
 
 template <class P>
 static hipError_t step_p(int bx, char* base, const LatDesc* descs, int nlat, int ntot, int src,
-                         int grid, hipStream_t s)
+                         int grid, int ly, hipStream_t s)
 {
     switch (bx) {
-    case 64: return step_bx<64, P>(base, descs, nlat, ntot, src, grid, s);
-    case 128: return step_bx<128, P>(base, descs, nlat, ntot, src, grid, s);
-    case 256: return step_bx<256, P>(base, descs, nlat, ntot, src, grid, s);
+    case 64: return step_bx<64, P>(base, descs, nlat, ntot, src, grid, ly, s);
+    case 128: return step_bx<128, P>(base, descs, nlat, ntot, src, grid, ly, s);
+    case 256: return step_bx<256, P>(base, descs, nlat, ntot, src, grid, ly, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -642,9 +697,9 @@ static hipError_t step_p(int bx, char* base, const LatDesc* descs, int nlat, int
     }
 
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, int nlat, int ntot,
-                       int src, int grid, hipStream_t s)
+                       int src, int grid, int ly, hipStream_t s)
 {
-    LBK_DISPATCH(storage, (step_p<P>(bx, base, descs, nlat, ntot, src, grid, s)));
+    LBK_DISPATCH(storage, (step_p<P>(bx, base, descs, nlat, ntot, src, grid, ly, s)));
 }
 
 static int grid_for(long long n, int threads)

@@ -76,6 +76,10 @@ def load_library(path=LIB_PATH):
         "lb_time": [H, ctypes.POINTER(ctypes.c_int64)],
         "lb_time_steps": [H, ctypes.c_int32, _DP],
         "lb_destroy": [H],
+        "lb_autotune": [H, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_int32), _DP],
+        "lbb_autotune": [H, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _DP],
         "lbb_state_bytes": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
         "lbb_init": [P, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, DPP, DPP, DPP, DPP, ctypes.POINTER(H)],
         "lbb_step": [H, ctypes.c_int32],
@@ -266,6 +270,13 @@ class Lattice:
     def set_graph(self, steps_per_graph):
         _check(_lib.lb_set_graph(self._h, int(steps_per_graph)))
 
+    def autotune(self, cache_path=None, steps=20):
+        """Pick the fastest launch shape (state preserved); returns (bx, ly, ms)."""
+        bx, ly, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(_lib.lb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(ms)))
+        return bx.value, ly.value, ms.value
+
     def time(self):
         t = ctypes.c_int64()
         _check(_lib.lb_time(self._h, ctypes.byref(t)))
@@ -374,6 +385,14 @@ class Batch:
         ms = ctypes.c_double()
         _check(_lib.lbb_time_steps(self._h, int(n), ctypes.byref(ms)))
         return ms.value
+
+    def autotune(self, cache_path=None, steps=10):
+        """Pick the fastest launch shape and grid (state preserved); returns (bx, ly, grid, ms)."""
+        bx, ly, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(_lib.lbb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(grid),
+                                 ctypes.byref(ms)))
+        return bx.value, ly.value, grid.value, ms.value
 
     def close(self):
         if self._h:

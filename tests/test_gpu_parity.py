@@ -275,3 +275,25 @@ def test_reduced_precision_error_vs_oracle(init):
         e["mass_drift"] = float(np.max(np.abs(s[:2] - m0) / m0))
         print(f"\n{init} {storage}: {e}")
         assert max(e["rho_a"], e["rho_b"], e["jx"], e["jy"]) <= tol, (storage, e)
+
+
+def test_autotune_preserves_state_and_caches(tmp_path):
+    nx, ny = 256, 128
+    ra, rb = inputs.emulsion(nx, ny, seed=12)
+    ref = gpu_lattice(nx, ny, ra, rb, u_top=0.02, u_bot=-0.02, storage="f32", profile=True)
+    ref.step(10)
+    lat = gpu_lattice(nx, ny, ra, rb, u_top=0.02, u_bot=-0.02, storage="f32", profile=True)
+    lat.step(4)
+    cache = str(tmp_path / "tune.json")
+    bx, ly, ms = lat.autotune(cache, steps=3)
+    assert bx in (64, 128, 256) and ly >= 16 and ms > 0
+    assert lat.time() == 4
+    lat.step(6)
+    np.testing.assert_array_equal(lat.populations(), ref.populations())
+    assert lat.stress() == ref.stress()
+    import json
+    d = json.load(open(cache))
+    (key, ent), = d.items()
+    assert "f32/256x128" in key and ent["bx"] == bx and ent["ly"] == ly
+    lat2 = gpu_lattice(nx, ny, ra, rb, u_top=0.02, u_bot=-0.02, storage="f32")
+    assert lat2.autotune(cache, steps=3)[:2] == (bx, ly)     # from the cache
