@@ -12,8 +12,13 @@ Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
 step (18 population loads + 18 stores per site) divided by the step kernel's
 average duration, timed with HIP events on the lattice's stream.
 
+The launch shape comes from the project's autotuner (timed before the timed
+region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
+flow-curve points per hour on the batched 48-lattice ensemble (10 000 steps
+each) against a plain one-lattice-at-a-time loop.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--variants f32,f16dev,bf16dev] [--size 4096]
+       [--variants f32,f16dev,bf16dev] [--size 4096] [--no-flowcurve] [--no-tune]
 """
 import argparse
 import hashlib
@@ -53,7 +58,7 @@ def measured_traffic(workload, storage):
     return e.get("bytes_per_step")
 
 
-def gpu_run(storage, n, steps, warmup, u=0.02, seed=1):
+def gpu_run(storage, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
     import torch
     from paper_1004_5058_amd import inputs, lb
     ra, rb = inputs.emulsion(n, n, seed=seed)
@@ -61,6 +66,7 @@ def gpu_run(storage, n, steps, warmup, u=0.02, seed=1):
     lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=storage, profile=False,
                      **inputs.COUPLINGS)
     del ra, rb, ux, uy
+    shape = lat.autotune(tune_cache, steps=10) if tune_cache is not None else None
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -75,7 +81,37 @@ def gpu_run(storage, n, steps, warmup, u=0.02, seed=1):
     torch.cuda.empty_cache()
     lups = float(n) * n
     return dict(ms_per_step=1e3 * wall / steps, mlups=lups * steps / wall / 1e6,
-                ms_kernel=ms_kernel, stress=[sb, st], nsamples=ns)
+                ms_kernel=ms_kernel, stress=[sb, st], nsamples=ns,
+                shape=None if shape is None else {"bx": shape[0], "ly": shape[1]})
+
+
+def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
+    """Flow-curve points per hour on the batched ensemble (48 lattices, heights
+    256..1024, width 2H, U log-uniform in [1e-4, 5e-2], G^r in [7.5, 8.5]):
+    one persistent step kernel per time step for the whole batch, replayed as
+    HIP graphs, against the plain loop (one lattice at a time, one launch per
+    step, no graph).  Both produce the same per-lattice stresses."""
+    from paper_1004_5058_amd import flowcurve, inputs, lb
+    draws = inputs.ensemble(n_lat, seed=seed)
+    specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
+    sites = sum(s["nx"] * s["ny"] for s in specs)
+    if tune_cache is not None:
+        b = lb.Batch(specs, storage="f32", profile=True)
+        tuned = b.autotune(tune_cache, steps=3)
+        b.close()
+    else:
+        tuned = (0, 0, 0, 0.0)
+    rows_b, wall_b = flowcurve.run_batched(specs, steps, bx=tuned[0], ly=tuned[1], grid=tuned[2])
+    rows_p, wall_p = flowcurve.run_plain(specs, steps)
+    agree = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_b, rows_p))
+    return dict(lattices=n_lat, steps=steps, sites=sites,
+                batched_points_per_hour=round(n_lat * 3600.0 / wall_b, 1),
+                plain_points_per_hour=round(n_lat * 3600.0 / wall_p, 1),
+                batched_s=round(wall_b, 3), plain_s=round(wall_p, 3),
+                batched_mlups=round(sites * steps / wall_b / 1e6, 1),
+                plain_mlups=round(sites * steps / wall_p / 1e6, 1),
+                speedup=round(wall_p / wall_b, 3), max_sigma_mismatch=agree,
+                launch_shape={"bx": tuned[0], "ly": tuned[1], "grid": tuned[2]})
 
 
 def cpu_baseline(n, steps=3, u=0.02, seed=1):
@@ -103,6 +139,10 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--variants", default="f32,f16dev,bf16dev")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-flowcurve", action="store_true", help="skip the batched-vs-plain flow-curve leg")
+    ap.add_argument("--flow-steps", type=int, default=10000)
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"))
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
     a = ap.parse_args()
@@ -128,7 +168,7 @@ def main():
     variants = [v for v in a.variants.split(",") if v]
     res = {}
     for v in variants:
-        res[v] = gpu_run(v, n, a.steps, a.warmup)
+        res[v] = gpu_run(v, n, a.steps, a.warmup, tune_cache=None if a.no_tune else a.tune_cache)
         print(f"# {v}: {res[v]['mlups']:.0f} MLUPS, kernel {res[v]['ms_kernel']:.4f} ms/step", file=sys.stderr,
               flush=True)
     head = variants[0]
@@ -155,11 +195,18 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "variants": {v: {"mlups": round(res[v]["mlups"], 1), "ms_kernel": round(res[v]["ms_kernel"], 5),
+                         "launch_shape": res[v]["shape"],
                          "alg_gbs": round(BYTES_PER_LUP[v] * float(n) * n / (res[v]["ms_kernel"] * 1e-3) / 1e9, 1),
                          "bytes_per_lup": BYTES_PER_LUP[v]} for v in variants},
     }
     for v in variants:
         line["variants"][v]["frac"] = round(line["variants"][v]["alg_gbs"] / HBM_PEAK_GBS, 4)
+    if not a.no_flowcurve:
+        try:
+            line["flowcurve"] = flowcurve_rates(a.flow_steps, tune_cache=None if a.no_tune else a.tune_cache)
+            print(f"# flow curve: {line['flowcurve']}", file=sys.stderr, flush=True)
+        except Exception as e:  # reported, never hidden
+            line["flowcurve"] = {"error": repr(e)}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)

@@ -170,6 +170,12 @@ lb_status lb_autotune(lb_handle* h, const char* cache_path, int32_t steps, int32
 lb_status lbb_autotune(lbb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
                        int32_t* grid, double* ms);
 
+/* Achievable read+write HBM bandwidth: copies `bytes` (multiple of 16,
+ * 16-byte aligned device buffers) src -> dst `reps` times with a streaming
+ * 16-byte-per-lane kernel on hip_stream and returns (read + write bytes) /
+ * time in GB/s.  Synchronises.  A measurement reference, not part of a step. */
+lb_status lb_copy_peak(void* dst, const void* src, size_t bytes, void* hip_stream, int32_t reps, double* gbs);
+
 /* Steps taken since init (or restored by lb_load). */
 lb_status lb_time(lb_handle* h, int64_t* t);
 

@@ -653,7 +653,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     lb_status st = LB_OK;
     for (int bx : {64, 128, 256}) {
         if (bx > 64 && bx / 2 >= maxnx) continue;
-        for (int ly : {16, 32, 64, 128, 256}) {
+        for (int ly : {16, 32, 48, 64, 80, 96, 128, 160, 192, 256}) {
             if (ly > 16 && ly / 2 >= maxny) continue;
             std::vector<int> grids = {0};
             if (batch)
@@ -1018,6 +1018,33 @@ lb_status lbb_time_steps(lbb_handle* h, int32_t n, double* ms)
 {
     CHECK_H(h);
     return time_steps(h, n, ms);
+}
+
+lb_status lb_copy_peak(void* dst, const void* src, size_t bytes, void* hip_stream, int32_t reps, double* gbs)
+{
+    if (!dst || !src || !gbs || reps < 1 || bytes < 16 || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
+        return fail(LB_EINVAL, "copy needs 16-byte aligned buffers, a size multiple of 16 and reps >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0, ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        ncu = prop.multiProcessorCount;
+    const long long n16 = (long long)(bytes / 16);
+    const int blocks = (int)std::min<long long>((n16 + 255) / 256, (long long)ncu * 16);
+    HIP_TRY(lbk::launch_copy(src, dst, n16, blocks, s));   // warm-up
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(lbk::launch_copy(src, dst, n16, blocks, s));
+    HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return LB_OK;
 }
 
 lb_status lbb_autotune(lbb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,

@@ -115,6 +115,7 @@ template <class P> struct Row<P, false> {
     using C = typename P::C;
     C v[18];
     __device__ __forceinline__ C operator[](int q) const { return v[q]; }
+    // so: uniform SGPR byte offset of the row; voff: per-lane byte offset.
     __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned voff, int so, int pbytes)
     {
 #pragma unroll
@@ -275,8 +276,15 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         // 18 deviations of row r (any row; mapped through the walls or the
         // periodic wrap) at column byte offset voff.
         using R = Row<P>;
+        // 18 deviations of row r (uniform across the block; mapped through the
+        // walls or the periodic wrap) at column byte offset voff.
         auto load = [&](R& fr, int r, unsigned voff) {
-            fr.load(rin0, rin1, voff, map_row<P>(r, ny, walls) * rbytes, pbytes);
+            fr.load(rin0, rin1, voff + (unsigned)(map_row<P>(r, ny, walls) * rbytes), 0, pbytes);
+        };
+        // The same for a row that differs between lanes: the row goes into the
+        // per-lane offset and the SGPR offset keeps only the uniform plane.
+        auto load_lane = [&](R& fr, int r, unsigned voff) {
+            fr.load(rin0, rin1, voff + (unsigned)(map_row<P>(r, ny, walls) * rbytes), 0, pbytes);
         };
         auto dens = [&](const R& fr, C& da, C& db) {
             da = fr[0];
@@ -294,7 +302,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 hc %= nx;
                 if (hc < 0) hc += nx;
                 R h;
-                load(h, y0 - 2 + rr, (unsigned)hc * es);
+                load_lane(h, y0 - 2 + rr, (unsigned)hc * es);
                 C da, db;
                 dens(h, da, db);
                 C4 v;
@@ -310,7 +318,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         // Stage row r (populations already in fr): (dpsi, drho) into the ring,
         // plus the four halo entries copied by lanes 0..3.
         auto stage = [&](const R& fr, int r) {
-            const int slot = (r - y0 + 2) % 6;
+            const int slot = __builtin_amdgcn_readfirstlane((r - y0 + 2) % 6);
             C da, db;
             dens(fr, da, db);
             C2 pv, rv;
@@ -336,8 +344,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         // Collide row y (populations in f, neighbourhood in LDS) and push.
         auto collide = [&](const R& f, int y) {
             int sl[5];
+            sl[0] = __builtin_amdgcn_readfirstlane((y - y0) % 6);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sl[k] = (y + k - y0) % 6;
+            for (int k = 1; k < 5; ++k) sl[k] = (sl[k - 1] == 5) ? 0 : sl[k - 1] + 1;
             C sxA = 0, syA = 0, sxB = 0, syB = 0, cxA = 0, cyA = 0, cxB = 0, cyB = 0;
 #pragma unroll
             for (int dy = -2; dy <= 2; ++dy) {
@@ -389,6 +398,11 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
 
             const bool bot = walls && (y == 0);
             const bool top = walls && (y == ny - 1);
+            // byte offsets of the destination rows y-1, y, y+1 (periodic wrap in y;
+            // at a wall the row beyond it is never written)
+            const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+            const unsigned vrow_m = (unsigned)(ym * rbytes), vrow_0 = (unsigned)(y * rbytes),
+                           vrow_p = (unsigned)(yp * rbytes);
             // BGK relaxation of the deviations towards
             // f^eq_i - w_i rho_ref = w_i [drho + rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v)],
             // then the push of species s to the neighbours (bounce-back at walls).
@@ -414,23 +428,32 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 pair(6, 8, r2, d2, vy - vx);
                 if (!valid) return;
                 const rsrc_t ro = (s == 0) ? rout0 : rout1;
+                if (!(bot || top)) {
+                    // interior row: plain push to rows y-1, y, y+1 (periodic wrap)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const int cx = CX[i], cy = CY[i];
+                        const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
+                        const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
+                        st<P>(ro, vrow + vcol, i * pbytes, fs[i]);
+                    }
+                    return;
+                }
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     const int cx = CX[i], cy = CY[i];
                     if (cy < 0 && bot) {
                         const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
-                        st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
+                        st<P>(ro, vrow_0 + vc, OPP[i] * pbytes, back);
                         if (cx != 0) mom_b += (C)cx * (fs[i] + back);
                     } else if (cy > 0 && top) {
                         const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
-                        st<P>(ro, vc, OPP[i] * pbytes + y * rbytes, back);
+                        st<P>(ro, vrow_0 + vc, OPP[i] * pbytes, back);
                         if (cx != 0) mom_t += (C)cx * (fs[i] + back);
                     } else {
-                        int yt = y + cy;
-                        if (yt < 0) yt += ny;
-                        else if (yt >= ny) yt -= ny;
+                        const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
                         const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
-                        st<P>(ro, vcol, i * pbytes + yt * rbytes, fs[i]);
+                        st<P>(ro, vrow + vcol, i * pbytes, fs[i]);
                     }
                 }
             };
@@ -664,6 +687,16 @@ __global__ void k_fill(double* __restrict__ p, long long n, double v)
         p[k] = v;
 }
 
+// Streaming copy (16 bytes per lane per access): the achievable read+write
+// HBM bandwidth the step kernel is compared with.
+__global__ void __launch_bounds__(256)
+k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n)
+{
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
 // ---------------------------------------------------------- host launchers --
 
 template <int BX, class P>
@@ -784,6 +817,12 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n16);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int n
 hipError_t launch_stress_reduce(char* base, const LatDesc* descs, int nlat, double* out, hipStream_t s);
 hipError_t launch_profile_reduce(char* base, const LatDesc* d, int ny, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t s);
 int sums_blocks();
 
 }  // namespace lbk

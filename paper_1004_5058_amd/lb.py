@@ -52,6 +52,10 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded, so device memory and streams from torch are valid in its calls
+    # (a second runtime instance in the process would not see them).
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     st = ctypes.c_int
     P = ctypes.POINTER(lb_params)
@@ -80,6 +84,7 @@ def load_library(path=LIB_PATH):
                         ctypes.POINTER(ctypes.c_int32), _DP],
         "lbb_autotune": [H, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _DP],
+        "lb_copy_peak": [_VP, _VP, ctypes.c_size_t, _VP, ctypes.c_int32, _DP],
         "lbb_state_bytes": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
         "lbb_init": [P, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, DPP, DPP, DPP, DPP, ctypes.POINTER(H)],
         "lbb_step": [H, ctypes.c_int32],
@@ -209,6 +214,18 @@ def lb_sums(h):
 def lb_destroy(h):
     if h:
         _check(_lib.lb_destroy(h))
+
+
+def copy_peak(nbytes=2 ** 31, reps=10, device="cuda:0"):
+    """Read+write GB/s of the library's streaming copy kernel on nbytes."""
+    torch = _torch()
+    L = load_library()
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    g = ctypes.c_double()
+    _check(L.lb_copy_peak(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                          _stream_handle(torch.device(device)), int(reps), ctypes.byref(g)))
+    return g.value
 
 
 # ------------------------------------------------------------- wrappers ---

@@ -27,10 +27,12 @@ def _net(X, y, seed=1):
     theta = M.init_params(seed).astype(np.float32)
     net.set_params(theta)
     mu, sd = X.mean(0), X.std(0)
-    net.set_norm(mu, sd, float(y.mean()), float(y.std()))
+    sd = np.where(sd > 0, sd, 1.0).astype(np.float32)
+    ysd = float(y.std()) if y.std() > 0 else 1.0
+    net.set_norm(mu, sd, float(y.mean()), ysd)
     net.set_data(X, y)
     Xs = (X.astype(np.float64) - mu) / sd
-    ys = (y.astype(np.float64) - float(y.mean())) / float(y.std())
+    ys = (y.astype(np.float64) - float(y.mean())) / ysd
     return net, theta.astype(np.float64), Xs, ys
 
 

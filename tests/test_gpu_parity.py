@@ -297,3 +297,17 @@ def test_autotune_preserves_state_and_caches(tmp_path):
     assert "f32/256x128" in key and ent["bx"] == bx and ent["ly"] == ly
     lat2 = gpu_lattice(nx, ny, ra, rb, u_top=0.02, u_bot=-0.02, storage="f32")
     assert lat2.autotune(cache, steps=3)[:2] == (bx, ly)     # from the cache
+
+
+def test_flowcurve_batched_equals_plain_loop():
+    """The batched ensemble path (one persistent launch per step, HIP graphs)
+    and the plain per-lattice loop give the same stresses and profiles."""
+    from paper_1004_5058_amd import flowcurve
+    draws = inputs.ensemble(5, seed=7, heights=(32, 48, 64), u_range=(1e-3, 3e-2))
+    specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
+    rb, _ = flowcurve.run_batched(specs, 120, bx=64, ly=16, grid=16, graph=8)
+    rp, _ = flowcurve.run_plain(specs, 120)
+    for a, b in zip(rb, rp):
+        assert a["sigma_bot"] == b["sigma_bot"] and a["sigma_top"] == b["sigma_top"]
+        assert a["S_bulk"] == b["S_bulk"]
+        assert a["S"] == pytest.approx(2 * a["u_wall"] / a["ny"])
