@@ -102,7 +102,9 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     else:
         tuned = (0, 0, 0, 0.0)
     rows_b, wall_b = flowcurve.run_batched(specs, steps, bx=tuned[0], ly=tuned[1], grid=tuned[2])
+    print(f"# flow curve: batched {n_lat} lattices x {steps} steps in {wall_b:.2f} s", file=sys.stderr, flush=True)
     rows_p, wall_p = flowcurve.run_plain(specs, steps)
+    print(f"# flow curve: plain loop in {wall_p:.2f} s", file=sys.stderr, flush=True)
     agree = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_b, rows_p))
     return dict(lattices=n_lat, steps=steps, sites=sites,
                 batched_points_per_hour=round(n_lat * 3600.0 / wall_b, 1),

@@ -183,13 +183,16 @@ template <class C> struct V2;
 template <> struct V2<float> { using T = float2; };
 template <> struct V2<double> { using T = double2; };
 
-// Workgroup barrier that orders LDS only: global loads issued before it stay
-// in flight (the row prefetch), unlike __syncthreads().
+// Workgroup barrier that orders LDS only: this wave's LDS reads and writes
+// complete (lgkmcnt 0), then s_barrier.  Global loads issued before it stay in
+// flight (the row prefetch), and so do direct-to-LDS halo loads: only the wave
+// that issued those reads their data, behind its own vmcnt wait.
 __device__ __forceinline__ void lds_barrier()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // gfx9 encoding: lgkmcnt(0), vmcnt/expcnt unchanged
     __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    asm volatile("" ::: "memory");
 }
 
 // Largest segment (rows per tile).
@@ -215,6 +218,13 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
     __shared__ C2 ringP[6][BX + 4];
     __shared__ C2 ringR[6][BX + 4];
     extern __shared__ __align__(16) char dyn_lds[];
+    // The four halo columns of a row arrive by direct buffer-to-LDS dword
+    // loads (no registers), one row ahead, in a four-row ring: one dword per
+    // column for 4-byte storage, one dword per column pair for 2-byte storage
+    // (pairs x0-2, x0-1 and x0+BX, x0+BX+1; needs an even nx).  Otherwise the
+    // halo of a whole tile is staged once per tile.
+    constexpr bool DMA32 = (sizeof(S) == 4), DMA16 = (sizeof(S) == 2);
+    __shared__ unsigned hst[(DMA32 || DMA16) ? 4 : 1][18][4];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -267,6 +277,17 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         const int es = (int)sizeof(S);
         const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
         const int pbytes = (int)(plane * es), rbytes = pitch * es;
+        const bool dma_halo = DMA32 || (DMA16 && (nx % 2) == 0);
+        // DMA lanes: byte offset of halo column x0-2, x0-1, x0+BX, x0+BX+1
+        // (4-byte storage, lanes 0..3) or of the pairs (2-byte storage, lanes 0..1)
+        unsigned vh = 0;
+        if (tid < 4) {
+            int hc = DMA16 ? ((tid == 0) ? x0 - 2 : x0 + BX) : ((tid < 2) ? x0 - 2 + tid : x0 + BX + tid - 2);
+            hc %= nx;
+            if (hc < 0) hc += nx;
+            vh = (unsigned)hc * es;
+        }
+        const int ndma = DMA16 ? 2 : 4;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
         C4* halo = (C4*)dyn_lds;                                       // [(ly + 4) * 4]
@@ -293,8 +314,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
             for (int q = 1; q < 9; ++q) { da += fr[q]; db += fr[9 + q]; }
         };
 
-        // Halo columns x0-2, x0-1, x0+BX, x0+BX+1 for every row of the segment.
-        {
+        // Halo columns x0-2, x0-1, x0+BX, x0+BX+1 for every row of the segment
+        // (formats without the direct-to-LDS halo).
+        if (!dma_halo) {
             const int nh = (y1 - y0 + 4) * 4;
             for (int s = tid; s < nh; s += BX) {
                 const int c = s & 3, rr = s >> 2;
@@ -313,10 +335,36 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
                 halo[rr * 4 + c] = v;
             }
         }
-        lds_barrier();
+        if (!dma_halo) lds_barrier();
+
+        // Issue the direct-to-LDS loads of row r's four halo columns (lanes 0..3).
+        auto halo_fetch = [&](int r) {
+            if constexpr (DMA32 || DMA16) {
+                if (dma_halo && tid < ndma) {
+                    const unsigned vo = vh + (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+#pragma unroll
+                    for (int q = 0; q < 18; ++q)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
+                            __builtin_amdgcn_readfirstlane((q % 9) * pbytes), 0, 0);
+                }
+            }
+        };
+        // Halo column value of plane q for lane tid (0..3) from the DMA ring.
+        auto hval = [&](int r, int q) -> C {
+            if constexpr (DMA32) {
+                return (C)__builtin_bit_cast(float, hst[r & 3][q][tid]);
+            } else if constexpr (DMA16) {
+                const unsigned wv = hst[r & 3][q][tid >> 1];
+                const unsigned short h = (unsigned short)((tid & 1) ? (wv >> 16) : (wv & 0xffffu));
+                return (C)__builtin_bit_cast(S, h);
+            } else {
+                return (C)0;
+            }
+        };
 
         // Stage row r (populations already in fr): (dpsi, drho) into the ring,
-        // plus the four halo entries copied by lanes 0..3.
+        // plus the four halo entries (lanes 0..3).
         auto stage = [&](const R& fr, int r) {
             const int slot = __builtin_amdgcn_readfirstlane((r - y0 + 2) % 6);
             C da, db;
@@ -329,13 +377,29 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
             ringP[slot][tid + 2] = pv;
             ringR[slot][tid + 2] = rv;
             if (tid < 4) {
-                const C4 hv = halo[(r - y0 + 2) * 4 + tid];
                 const int hidx = (tid < 2) ? tid : BX + tid;
                 C2 a, b;
-                a.x = hv.x;
-                a.y = hv.y;
-                b.x = hv.z;
-                b.y = hv.w;
+                if (dma_halo) {
+                    // the row's own loads have completed (da, db above); the halo
+                    // loads were issued before them, so their data is in LDS
+                    asm volatile("" ::"v"(da), "v"(db) : "memory");
+                    C ha = hval(r, 0), hb = hval(r, 9);
+#pragma unroll
+                    for (int q = 1; q < 9; ++q) {
+                        ha += hval(r, q);
+                        hb += hval(r, 9 + q);
+                    }
+                    a.x = dpsi_of(ha, e0, inv_rho0);
+                    a.y = dpsi_of(hb, e1, inv_rho0);
+                    b.x = ha;
+                    b.y = hb;
+                } else {
+                    const C4 hv = halo[(r - y0 + 2) * 4 + tid];
+                    a.x = hv.x;
+                    a.y = hv.y;
+                    b.x = hv.z;
+                    b.y = hv.w;
+                }
                 ringP[slot][hidx] = a;
                 ringR[slot][hidx] = b;
             }
@@ -462,21 +526,30 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
         };
 
         // Pipeline: entering iteration y, rows y and y+1 are staged and held,
-        // row y+2 is loaded (in flight); the iteration issues row y+3's loads,
-        // stages row y+2, waits on the LDS barrier and collides row y.
+        // row y+2 is loaded (in flight); the iteration stages row y+2, issues
+        // row y+3's loads, waits on the LDS barrier and collides row y.
+        // A row's halo loads are issued just before its own loads.
         R F0, F1, F2, F3;
+        halo_fetch(y0 - 2);
         load(F2, y0 - 2, vc);
+        halo_fetch(y0 - 1);
         load(F3, y0 - 1, vc);
         stage(F2, y0 - 2);
         stage(F3, y0 - 1);
+        halo_fetch(y0);
         load(F0, y0, vc);
+        halo_fetch(y0 + 1);
         load(F1, y0 + 1, vc);
+        halo_fetch(y0 + 2);
         load(F2, y0 + 2, vc);
         stage(F0, y0);
         stage(F1, y0 + 1);
         auto iter = [&](int y, const R& fc, const R& fs2, R& fl) {
-            if (y + 3 <= y1 + 1) load(fl, y + 3, vc);
             stage(fs2, y + 2);
+            if (y + 3 <= y1 + 1) {
+                halo_fetch(y + 3);
+                load(fl, y + 3, vc);
+            }
             lds_barrier();
             collide(fc, y);
         };

@@ -311,3 +311,19 @@ def test_flowcurve_batched_equals_plain_loop():
         assert a["sigma_bot"] == b["sigma_bot"] and a["sigma_top"] == b["sigma_top"]
         assert a["S_bulk"] == b["S_bulk"]
         assert a["S"] == pytest.approx(2 * a["u_wall"] / a["ny"])
+
+
+@pytest.mark.parametrize("storage,nx,ny,tol", [("f16dev", 129, 40, 6e-5), ("bf16dev", 130, 40, 5e-4),
+                                               ("f32", 131, 41, 1e-7), ("f16dev", 64, 37, 6e-5)])
+def test_reduced_precision_odd_and_even_widths(storage, nx, ny, tol):
+    """16-bit storage stages the halo of an odd-width lattice per tile and of an
+    even-width one by paired direct-to-LDS loads; both match the oracle."""
+    u = 0.02
+    ra, rb = inputs.noise(nx, ny, seed=2)
+    p = oracle_params(nx, ny, True, u, -u)
+    g, _, _ = oracle_run(p, ra, rb, None, None, 60)
+    for bx in (64, 128):
+        lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage)
+        lat.set_launch(bx, 16)
+        lat.step(60)
+        compare_fields(lat, p, g, tol)
