@@ -1,0 +1,118 @@
+"""Full-size checks: the 4096x4096 benchmark workload in the launch shape the
+benchmark times (from the committed tuning cache), against the FP64 oracle on
+sampled windows, and through properties that hold at any size.
+
+Windowed parity: after k steps a site depends only on the initial state
+within distance 3k (one site of streaming plus two of the force stencil per
+step).  The oracle therefore runs on a window around each sample with a
+margin of 3k sites; the margin's own boundary (periodic, or the lattice's
+real wall plus a fake one) cannot reach the sampled centre."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import CS, need_gpu, oracle_params
+from oracle import oracle as O
+from paper_1004_5058_amd import inputs
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+N, U = 4096, 0.02
+
+
+@pytest.fixture(scope="module")
+def big():
+    need_gpu()
+    from paper_1004_5058_amd import lb
+    ra, rb = inputs.emulsion(N, N, seed=1)
+    ux, uy = inputs.couette(N, N, U, -U)
+    lat = lb.Lattice(N, N, ra, rb, ux, uy, u_top=U, u_bot=-U, storage="f32", **inputs.COUPLINGS)
+    bx, ly, _ = lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
+    yield lat, ra, rb, ux, uy, (bx, ly)
+    lat.close()
+
+
+def _window(a, x0, y0, w, h):
+    xs = np.arange(x0, x0 + w) % N
+    return np.ascontiguousarray(a[y0:y0 + h][:, xs])
+
+
+def test_sampled_windows_match_oracle(big):
+    lat, ra, rb, ux, uy, shape = big
+    k = 3
+    m = 3 * k
+    lat.step(k)
+    ga, gb, gux, guy = lat.fields()
+    w = 24
+    cases = [(1000, 2000, "interior"), (4090, 17, "interior-wrap"), (77, 0, "bottom"), (2500, N - (w + m), "top")]
+    for x0, y0, kind in cases:
+        if kind.startswith("interior"):
+            xs, ys, hw = x0 - m, y0 - m, w + 2 * m
+            p = oracle_params(hw, hw, False, 0, 0)
+            cut = (slice(m, m + w), slice(m, m + w))
+            gy = slice(y0, y0 + w)
+        elif kind == "bottom":
+            xs, ys, hw = x0 - m, 0, w + 2 * m
+            p = oracle_params(hw, w + m, True, U, -U)
+            cut = (slice(0, w), slice(m, m + w))
+            gy = slice(0, w)
+        else:
+            xs, ys, hw = x0 - m, N - (w + m), w + 2 * m
+            p = oracle_params(hw, w + m, True, U, -U)
+            cut = (slice(m, m + w), slice(m, m + w))
+            gy = slice(N - w, N)
+        hh = p.ny
+        f = O.init(p, _window(ra, xs, ys, hw, hh), _window(rb, xs, ys, hw, hh),
+                   _window(ux, xs, ys, hw, hh), _window(uy, xs, ys, hw, hh))
+        g, _, _ = O.run(p, f, k)
+        oa, ob, oux, ouy = [a[cut] for a in O.fields(p, g)]
+        gxs = np.arange(x0, x0 + w) % N
+        sa, sb = ga[gy][:, gxs], gb[gy][:, gxs]
+        su, sv = gux[gy][:, gxs], guy[gy][:, gxs]
+        e_rho = max(np.max(np.abs(sa - oa)), np.max(np.abs(sb - ob))) / 1.0
+        e_j = max(np.max(np.abs(su * (sa + sb) - oux * (oa + ob))),
+                  np.max(np.abs(sv * (sa + sb) - ouy * (oa + ob)))) / (1.1 * CS)
+        print(f"{kind} window at ({x0},{y0}), shape {shape}: rho {e_rho:.2e}, j {e_j:.2e}")
+        assert e_rho < 1e-6 and e_j < 1e-6, (kind, e_rho, e_j)
+
+
+def test_conservation_and_wall_budget(big):
+    """Per-species mass is exact with moving walls, and the fluid's x momentum
+    changes by minus the momentum the walls receive, at the full size."""
+    lat = big[0]
+    s0 = lat.sums()
+    lat.stress_reset()
+    lat.step(1)
+    s1 = lat.sums()
+    sb, st, n = lat.stress()
+    assert n == 1
+    assert abs(s1[0] - s0[0]) / s0[0] < 1e-7 and abs(s1[1] - s0[1]) / s0[1] < 1e-7
+    f_bot, f_top = sb * N, -st * N           # x momentum received by the walls this step
+    budget = (s1[2] - s0[2]) + (f_bot + f_top)
+    print(f"dPx {s1[2] - s0[2]:.6e}, walls {f_bot + f_top:.6e}, residual {budget:.3e}")
+    assert abs(budget) < 1e-3 * max(abs(f_bot), abs(f_top), 1.0)
+    assert s1[4] == 0
+
+
+def test_full_size_1024_against_oracle():
+    """The 1024x1024 FP32 Couette workload (wall speed 0.05), whole lattice,
+    20 steps, every site and the time-averaged wall stress."""
+    need_gpu()
+    from paper_1004_5058_amd import lb
+    n, u, steps = 1024, 0.05, 20
+    ra, rb = inputs.emulsion(n, n, seed=1)
+    ux, uy = inputs.couette(n, n, u, -u)
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage="f32", **inputs.COUPLINGS)
+    lat.step(steps)
+    ga, gb, gux, guy = lat.fields()
+    sb, st, _ = lat.stress()
+    p = oracle_params(n, n, True, u, -u)
+    f = O.init(p, ra, rb, ux, uy)
+    g, osb, ost = O.run(p, f, steps)
+    oa, ob, oux, ouy = O.fields(p, g)
+    e_rho = max(np.max(np.abs(ga - oa)), np.max(np.abs(gb - ob)))
+    e_j = np.max(np.abs(gux * (ga + gb) - oux * (oa + ob))) / (1.1 * CS)
+    e_s = max(abs(sb - osb / steps) / abs(osb / steps), abs(st - ost / steps) / abs(ost / steps))
+    print(f"1024^2 FP32, {steps} steps: rho {e_rho:.2e}, j {e_j:.2e}, sigma {e_s:.2e}")
+    assert e_rho < 1e-6 and e_j < 1e-6 and e_s < 1e-5
