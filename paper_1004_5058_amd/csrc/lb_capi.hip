@@ -92,7 +92,8 @@ struct Lat {
 
 // Layout: [descs][partials][results] then per lattice [f0][f1][stress][prof].
 struct Layout {
-    size_t off_desc = 0, off_part = 0, off_res = 0, total = 0;
+    size_t off_desc = 0, off_part = 0, off_res = 0, off_tiles = 0, total = 0;
+    int max_items = 0;   // capacity of the item -> lattice table (any launch shape)
 };
 
 Layout plan(std::vector<Lat>& lats)
@@ -103,7 +104,13 @@ Layout plan(std::vector<Lat>& lats)
     L.off_part = align_up(sizeof(lbk::LatDesc) * n, ALIGN);
     L.off_res = L.off_part + align_up(sizeof(double) * 5 * lbk::sums_blocks(), ALIGN);
     // results: 5 sums + flag slot + 2 per lattice stress + profile staging handled in f buffers
-    size_t off = L.off_res + align_up(sizeof(double) * (8 + 2 * n), ALIGN);
+    // Item -> lattice table: at most ceil(nx/64) * ny items per lattice (the
+    // narrowest tile, one row per segment) plus 7 alignment slots each.
+    long long items = 0;
+    for (const auto& a : lats) items += (long long)((a.p.nx + 63) / 64) * a.p.ny + 7;
+    L.max_items = (int)std::min<long long>(items, INT32_MAX);
+    L.off_tiles = L.off_res + align_up(sizeof(double) * (8 + 2 * n), ALIGN);
+    size_t off = L.off_tiles + align_up(sizeof(int32_t) * (size_t)L.max_items, ALIGN);
     for (auto& a : lats) {
         const size_t es = storage_size(a.p.storage);
         a.pitch = (int)align_up((size_t)a.p.nx, 64);
@@ -200,6 +207,8 @@ struct lbb_handle {
     double* d_res() { return (double*)(base + lay.off_res); }
     int* d_flag() { return (int*)(base + lay.off_res + 6 * sizeof(double)); }
     lbk::LatDesc* d_desc() { return (lbk::LatDesc*)(base + lay.off_desc); }
+    int32_t* d_tiles() { return (int32_t*)(base + lay.off_tiles); }
+    std::vector<int32_t> tiles;      // host copy of the item -> lattice table
 };
 
 struct lb_handle {
@@ -215,11 +224,13 @@ void drop_graphs(lbb_handle* h)
 }
 
 // Work decomposition for launch shape (bx, ly): tiles per lattice, each
-// lattice's first item rounded up to a multiple of 8 (one tile per XCD slot).
+// lattice's first item rounded up to a multiple of 8 (one tile per XCD slot),
+// and the item -> lattice table the step kernel reads (-1: padding).
 lb_status decompose(lbb_handle* h)
 {
     int item = 0;
     h->ly_max = 1;
+    h->tiles.clear();
     for (size_t k = 0; k < h->lats.size(); ++k) {
         const Lat& a = h->lats[k];
         lbk::LatDesc& d = h->descs[k];
@@ -231,9 +242,14 @@ lb_status decompose(lbb_handle* h)
         item = (item + 7) / 8 * 8;
         d.item_begin = item;
         item += d.nitems;
+        h->tiles.resize(d.item_begin, -1);
+        h->tiles.resize(item, (int32_t)k);
     }
+    if (item > h->lay.max_items) return fail(LB_EINVAL, "launch shape gives more work items than planned");
     h->ntot = item;
     HIP_TRY(hipMemcpyAsync(h->d_desc(), h->descs.data(), sizeof(lbk::LatDesc) * h->descs.size(),
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_tiles(), h->tiles.data(), sizeof(int32_t) * h->tiles.size(),
                            hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     drop_graphs(h);
@@ -248,7 +264,7 @@ int launch_grid(const lbb_handle* h)
 
 lb_status launch_one(lbb_handle* h, hipStream_t s, int src)
 {
-    hipError_t e = lbk::launch_step(h->storage, h->bx, h->base, h->d_desc(), (int)h->lats.size(),
+    hipError_t e = lbk::launch_step(h->storage, h->bx, h->base, h->d_desc(), h->d_tiles(),
                                     h->ntot, src, launch_grid(h), h->ly_max, s);
     if (e != hipSuccess) return fail(LB_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
     return LB_OK;
@@ -346,6 +362,8 @@ lb_status reset_acc(lbb_handle* h)
     return LB_OK;
 }
 
+void default_shape(lbb_handle* h);
+
 lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t bytes, void* stream,
                      const double* const* ra, const double* const* rb, const double* const* ux,
                      const double* const* uy, lbb_handle** out)
@@ -390,11 +408,7 @@ lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t
     h->stream = (hipStream_t)stream;
     h->descs.resize(n);
     for (int k = 0; k < n; ++k) fill_desc(lats[k], h->descs[k]);
-    // Default launch shape: 256 columns per block where the lattices are wide enough.
-    int maxnx = 0;
-    for (const Lat& a : lats) maxnx = std::max(maxnx, a.p.nx);
-    h->bx = maxnx >= 256 ? 256 : (maxnx >= 128 ? 128 : 64);
-    h->ly = 64;
+    default_shape(h);
     lb_status st = decompose(h);
     if (st != LB_OK) { delete h; return st; }
 
@@ -482,6 +496,32 @@ lb_status profile_one(lbb_handle* h, int k, double* prof, int64_t* ns)
     for (int y = 0; y < a.p.ny; ++y) prof[y] = h->nsamples > 0 ? prof[y] / m : 0.0;
     if (ns) *ns = h->nsamples;
     return LB_OK;
+}
+
+// Default launch shape: the widest tile and tallest row segment that still
+// give about sixteen work items per compute unit.  A block marches its segment
+// row by row and each row waits on memory, so small lattices and small
+// batches split into a few tall items leave the chip idle; big lattices keep
+// wide, tall items (fewer segment prologues and halo columns).
+void default_shape(lbb_handle* h)
+{
+    int dev = 0, ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        ncu = prop.multiProcessorCount;
+    int maxnx = 0;
+    for (const Lat& a : h->lats) maxnx = std::max(maxnx, a.p.nx);
+    const int bxmax = maxnx >= 256 ? 256 : (maxnx >= 128 ? 128 : 64);
+    static const int cand[][2] = {{256, 64}, {256, 32}, {256, 16}, {128, 16}, {64, 16}, {64, 8}};
+    for (const auto& c : cand) {
+        if (c[0] > bxmax) continue;
+        long long items = 0;
+        for (const Lat& a : h->lats)
+            items += (long long)((a.p.nx + c[0] - 1) / c[0]) * ((a.p.ny + c[1] - 1) / c[1]);
+        h->bx = c[0];
+        h->ly = c[1];
+        if (items >= 16ll * ncu) return;
+    }
 }
 
 lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
@@ -653,7 +693,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     lb_status st = LB_OK;
     for (int bx : {64, 128, 256}) {
         if (bx > 64 && bx / 2 >= maxnx) continue;
-        for (int ly : {16, 32, 48, 64, 80, 96, 128, 160, 192, 256}) {
+        for (int ly : {8, 16, 32, 48, 64, 80, 96, 128, 160, 192, 256}) {
             if (ly > 16 && ly / 2 >= maxny) continue;
             std::vector<int> grids = {0};
             if (batch)

@@ -208,7 +208,8 @@ __host__ __device__ constexpr size_t step_dyn_lds(int bx, int ly)
 
 template <int BX, class P>
 __global__ void __launch_bounds__(BX)
-k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int ntot, int src)
+k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __restrict__ tiles, int ntot,
+       int src)
 {
     using S = typename P::S;
     using C = typename P::C;
@@ -230,9 +231,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, int nlat, int
     const int wave = tid >> 6;
 
     for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
-        int L = 0;
-        for (int k = 1; k < nlat; ++k)
-            if (descs[k].item_begin <= w) L = k;
+        const int L = tiles[w];          // owning lattice, -1 for alignment padding
+        if (L < 0) continue;
         const LatDesc& d = descs[L];
         const int l = w - d.item_begin;
         if (l >= d.nitems) continue;
@@ -773,22 +773,22 @@ k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n)
 // ---------------------------------------------------------- host launchers --
 
 template <int BX, class P>
-static hipError_t step_bx(char* base, const LatDesc* descs, int nlat, int ntot, int src, int grid,
+static hipError_t step_bx(char* base, const LatDesc* descs, const int* tiles, int ntot, int src, int grid,
                           int ly, hipStream_t s)
 {
     const size_t dyn = step_dyn_lds<typename P::C>(BX, ly);
-    hipLaunchKernelGGL((k_step<BX, P>), dim3(grid), dim3(BX), dyn, s, base, descs, nlat, ntot, src);
+    hipLaunchKernelGGL((k_step<BX, P>), dim3(grid), dim3(BX), dyn, s, base, descs, tiles, ntot, src);
     return hipGetLastError();
 }
 
 template <class P>
-static hipError_t step_p(int bx, char* base, const LatDesc* descs, int nlat, int ntot, int src,
+static hipError_t step_p(int bx, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
                          int grid, int ly, hipStream_t s)
 {
     switch (bx) {
-    case 64: return step_bx<64, P>(base, descs, nlat, ntot, src, grid, ly, s);
-    case 128: return step_bx<128, P>(base, descs, nlat, ntot, src, grid, ly, s);
-    case 256: return step_bx<256, P>(base, descs, nlat, ntot, src, grid, ly, s);
+    case 64: return step_bx<64, P>(base, descs, tiles, ntot, src, grid, ly, s);
+    case 128: return step_bx<128, P>(base, descs, tiles, ntot, src, grid, ly, s);
+    case 256: return step_bx<256, P>(base, descs, tiles, ntot, src, grid, ly, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -802,10 +802,10 @@ static hipError_t step_p(int bx, char* base, const LatDesc* descs, int nlat, int
     default: return hipErrorInvalidValue;                            \
     }
 
-hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, int nlat, int ntot,
+hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int grid, int ly, hipStream_t s)
 {
-    LBK_DISPATCH(storage, (step_p<P>(bx, base, descs, nlat, ntot, src, grid, ly, s)));
+    LBK_DISPATCH(storage, (step_p<P>(bx, base, descs, tiles, ntot, src, grid, ly, s)));
 }
 
 static int grid_for(long long n, int threads)

@@ -8,7 +8,7 @@
 namespace lbk {
 
 // ly: the largest rows-per-tile of the lattices (sizes the dynamic LDS).
-hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, int nlat, int ntot,
+hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int grid, int ly, hipStream_t s);
 hipError_t launch_init(int storage, char* base, const LatDesc* d, long long nsites, int buf,
                        const double* ra, const double* rb, const double* ux, const double* uy,

@@ -100,6 +100,20 @@ class FlowSurrogate:
         sk = (fit["sigma_y"] / fit["B"]) ** (1.0 / fit["beta"])
         return float(np.clip(sk, S_lo, S_hi)), fit
 
+    def curve(self, g1, g2):
+        """The network's curve x = log S -> asinh target at fixed couplings."""
+        return lambda x: to_target(self.predict(g1, g2, np.exp(np.asarray(x, dtype=np.float64))))
+
+    def root(self, g1, g2, sigma_target, S_lo, S_hi, n=512):
+        """The network's shear rate for sigma_target on [S_lo, S_hi] (grid
+        point nearest in asinh space) and its local slope dt/dlog S there."""
+        x = np.linspace(np.log(S_lo), np.log(S_hi), n)
+        t = to_target(self.predict(g1, g2, np.exp(x)))
+        k = int(np.argmin(np.abs(t - to_target(sigma_target))))
+        a, b = max(k - 2, 0), min(k + 2, n - 1)
+        slope = (t[b] - t[a]) / (x[b] - x[a])
+        return float(x[k]), float(slope)
+
     def propose(self, g1, g2, S_lo, S_hi, k=6, width=1.0):
         """k shear rates log-spaced within +-width decades of the knee."""
         sk, fit = self.knee(g1, g2, S_lo, S_hi)
@@ -117,3 +131,120 @@ def lb_flow_points(S_list, g1, g2, steps, ny=512, nx=1024, seed=500, storage="f3
                           seed=seed + k))
     specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
     return flowcurve.run_batched(specs, steps, storage=storage)
+
+
+
+class RateSolver:
+    """Stress-controlled point: the shear rate S in [S_lo, S_hi] at which a
+    lattice's time-averaged wall stress equals sigma_target, to a relative
+    tolerance tol, found from lattice runs only (every accepted point is a
+    lattice result; no method accepts a predicted stress).
+
+    Works in x = log S and t = asinh(sigma / SIGMA_UNIT), where a power-law
+    flow curve is close to a straight line.  method:
+      "bisect"   bisection of the bracket;
+      "secant"   safeguarded secant: starts at the bracket's midpoint with
+                 the Newtonian slope dt/dx = 1, then uses the slope through
+                 the last two lattice points (the previous slope if that is
+                 not positive); a step leaving the bracket, or one taken
+                 when three runs have not halved the bracket, is replaced
+                 by bisection;
+      "surrogate" starts at the network's root; after each lattice run it
+                 moves to the root of the network's curve shifted by that
+                 run's residual (t_lattice - t_network at the run's S), so
+                 the network supplies the shape of the curve and the
+                 lattice its level; same bracket and stall safeguards.
+                 model(x array) -> t array is the network's curve at the
+                 case's couplings.
+    A bracket narrower than min_width in log S with no accepted point means
+    the flow curve jumps across the target there (a discontinuous branch
+    change): the solver stops with jump = True and no result.
+    Driven by propose() -> S or None (done) and update(sigma)."""
+
+    def __init__(self, sigma_target, S_lo, S_hi, method="secant", x0=None, slope0=1.0, tol=0.01,
+                 max_runs=40, min_width=1e-3, model=None):
+        self.target = float(sigma_target)
+        self.tt = float(to_target(sigma_target))
+        self.lo, self.hi = np.log(S_lo), np.log(S_hi)
+        self.method = method
+        self.x = 0.5 * (self.lo + self.hi) if x0 is None else float(np.clip(x0, self.lo, self.hi))
+        self.slope = float(slope0)
+        self.tol = tol
+        self.max_runs = max_runs
+        self.runs = 0
+        self.prev = None
+        self.min_width = min_width
+        self.model = model
+        if method == "surrogate" and model is None:
+            raise ValueError("the surrogate method needs the network's curve")
+        self.widths = [self.hi - self.lo]
+        self.result = None          # (S, sigma) once accepted
+        self.jump = False
+
+    def propose(self):
+        if self.result is not None or self.jump or self.runs >= self.max_runs:
+            return None
+        return float(np.exp(self.x))
+
+    def update(self, sigma):
+        self.runs += 1
+        x, t = self.x, float(to_target(sigma))
+        if abs(sigma - self.target) <= self.tol * abs(self.target):
+            self.result = (float(np.exp(x)), float(sigma))
+            return
+        if t < self.tt:
+            self.lo = max(self.lo, x)
+        else:
+            self.hi = min(self.hi, x)
+        if self.hi - self.lo < self.min_width:
+            self.jump = True
+            return
+        mid = 0.5 * (self.lo + self.hi)
+        self.widths.append(self.hi - self.lo)
+        # secant steps that have not halved the bracket over three runs
+        # (a kink or a jump between the points) give way to bisection
+        stalled = len(self.widths) > 3 and self.widths[-1] > 0.5 * self.widths[-4]
+        if self.method == "bisect" or stalled:
+            self.x = mid
+            self.prev = (x, t)
+            return
+        if self.method == "surrogate":
+            self.prev = (x, t)
+            self.x = self._shifted_root(x, t, mid)
+            return
+        if self.prev is not None and self.prev[0] != x:
+            s = (t - self.prev[1]) / (x - self.prev[0])
+            if s > 0:
+                self.slope = s
+        self.prev = (x, t)
+        xn = x + (self.tt - t) / self.slope if self.slope > 0 else mid
+        self.x = xn if self.lo < xn < self.hi else mid
+
+    def _shifted_root(self, x, t, mid, n=257):
+        """Root inside the bracket of model(x') + (t - model(x)) = target,
+        linearly interpolated between grid points; the midpoint if the
+        shifted curve does not cross the target inside the bracket."""
+        c = t - float(self.model(np.array([x]))[0])
+        g = np.linspace(self.lo, self.hi, n)[1:-1]
+        r = np.asarray(self.model(g), dtype=np.float64) + c - self.tt
+        cross = np.nonzero(np.signbit(r[:-1]) != np.signbit(r[1:]))[0]
+        if cross.size == 0:
+            return mid
+        k = cross[np.argmin(np.abs(g[cross] - x))]       # the crossing nearest the last run
+        return float(g[k] - r[k] * (g[k + 1] - g[k]) / (r[k + 1] - r[k]))
+
+
+def solve_batched(solvers, lb_eval_many):
+    """Advance solvers in lockstep: each round gathers every open solver's
+    proposal and runs them as one lattice batch.  lb_eval_many(list of
+    (solver index, S)) -> list of sigma.  Returns the number of rounds."""
+    rounds = 0
+    while True:
+        todo = [(k, s.propose()) for k, s in enumerate(solvers)]
+        todo = [(k, S) for k, S in todo if S is not None]
+        if not todo:
+            return rounds
+        sig = lb_eval_many(todo)
+        for (k, _), v in zip(todo, sig):
+            solvers[k].update(v)
+        rounds += 1

@@ -286,7 +286,7 @@ def test_autotune_preserves_state_and_caches(tmp_path):
     lat.step(4)
     cache = str(tmp_path / "tune.json")
     bx, ly, ms = lat.autotune(cache, steps=3)
-    assert bx in (64, 128, 256) and ly >= 16 and ms > 0
+    assert bx in (64, 128, 256) and ly >= 8 and ms > 0
     assert lat.time() == 4
     lat.step(6)
     np.testing.assert_array_equal(lat.populations(), ref.populations())
