@@ -915,7 +915,7 @@ lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
     CkptHeader hd;
     std::memset(&hd, 0, sizeof hd);
     std::memcpy(hd.magic, "LBMI355", 8);
-    hd.version = 1;
+    hd.version = 2;   // 2: planes stored shifted in x by c_ix
     hd.storage = b->storage;
     hd.nx = a.p.nx;
     hd.ny = a.p.ny;
@@ -944,7 +944,7 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes)
     const Lat& a = b->lats[0];
     CkptHeader hd;
     std::memcpy(&hd, buf, sizeof hd);
-    if (std::memcmp(hd.magic, "LBMI355", 8) != 0 || hd.version != 1) return fail(LB_ESTATE, "not a checkpoint");
+    if (std::memcmp(hd.magic, "LBMI355", 8) != 0 || hd.version != 2) return fail(LB_ESTATE, "not a checkpoint");
     if (hd.storage != b->storage || hd.nx != a.p.nx || hd.ny != a.p.ny || hd.pitch != a.pitch ||
         hd.profile != a.p.profile)
         return fail(LB_ESTATE, "checkpoint of another lattice shape, storage or profile setting");

@@ -22,6 +22,7 @@
 // the halo columns and the two halo rows at each end of a segment.
 #include "lb_device.hpp"
 #include "lb_kernels.hpp"
+#include <type_traits>
 
 namespace lbk {
 
@@ -115,11 +116,17 @@ template <class P> struct Row<P, false> {
     using C = typename P::C;
     C v[18];
     __device__ __forceinline__ C operator[](int q) const { return v[q]; }
-    // so: uniform SGPR byte offset of the row; voff: per-lane byte offset.
-    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned voff, int so, int pbytes)
+    // Planes are stored shifted in x by c_ix: population q of the lane's node
+    // sits one column left (c_ix = +1: vl), in place (vc) or one column right
+    // (c_ix = -1: vr).  so: uniform SGPR byte offset; v*: per-lane byte offsets.
+    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, int so,
+                                         int pbytes)
     {
 #pragma unroll
-        for (int q = 0; q < 18; ++q) v[q] = ld<P>(q < 9 ? r0 : r1, voff, so + (q % 9) * pbytes);
+        for (int q = 0; q < 18; ++q) {
+            const int cx = CX[q % 9];
+            v[q] = ld<P>(q < 9 ? r0 : r1, cx > 0 ? vl : (cx < 0 ? vr : vc), so + (q % 9) * pbytes);
+        }
     }
 };
 
@@ -131,13 +138,17 @@ template <class P> struct Row<P, true> {
     {
         return (float)((q & 1) ? v[q >> 1].y : v[q >> 1].x);
     }
-    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned voff, int so, int pbytes)
+    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, int so,
+                                         int pbytes)
     {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const int q0 = 2 * k, q1 = 2 * k + 1;
-            v[k].x = bload<S>(q0 < 9 ? r0 : r1, voff, __builtin_amdgcn_readfirstlane(so + (q0 % 9) * pbytes));
-            v[k].y = bload<S>(q1 < 9 ? r0 : r1, voff, __builtin_amdgcn_readfirstlane(so + (q1 % 9) * pbytes));
+            const int c0 = CX[q0 % 9], c1 = CX[q1 % 9];
+            v[k].x = bload<S>(q0 < 9 ? r0 : r1, c0 > 0 ? vl : (c0 < 0 ? vr : vc),
+                              __builtin_amdgcn_readfirstlane(so + (q0 % 9) * pbytes));
+            v[k].y = bload<S>(q1 < 9 ? r0 : r1, c1 > 0 ? vl : (c1 < 0 ? vr : vc),
+                              __builtin_amdgcn_readfirstlane(so + (q1 % 9) * pbytes));
         }
     }
 };
@@ -220,12 +231,15 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
     __shared__ C2 ringR[6][BX + 4];
     extern __shared__ __align__(16) char dyn_lds[];
     // The four halo columns of a row arrive by direct buffer-to-LDS dword
-    // loads (no registers), one row ahead, in a four-row ring: one dword per
-    // column for 4-byte storage, one dword per column pair for 2-byte storage
-    // (pairs x0-2, x0-1 and x0+BX, x0+BX+1; needs an even nx).  Otherwise the
-    // halo of a whole tile is staged once per tile.
+    // loads (no registers), one row ahead, in a four-row ring.  4-byte
+    // storage: one dword per halo column and plane, taken from the plane's
+    // shifted column.  2-byte storage: three column pairs on each side,
+    // x0-4 .. x0+1 and x0+BX-2 .. x0+BX+3, which hold the four halo columns
+    // under every shift (needs an even nx).  Otherwise the halo of a whole
+    // tile is staged once per tile.
     constexpr bool DMA32 = (sizeof(S) == 4), DMA16 = (sizeof(S) == 2);
-    __shared__ unsigned hst[(DMA32 || DMA16) ? 4 : 1][18][4];
+    using HT = std::conditional_t<DMA16, unsigned short, unsigned>;
+    __shared__ HT hst[(DMA32 || DMA16) ? 4 : 1][18][DMA16 ? 12 : 4];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -275,19 +289,23 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const rsrc_t rin0 = make_rsrc(fin, sbytes), rin1 = make_rsrc(fin + sbytes, sbytes);
         const rsrc_t rout0 = make_rsrc(fout, sbytes), rout1 = make_rsrc(fout + sbytes, sbytes);
         const int es = (int)sizeof(S);
-        const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
+        const unsigned vc = xc * es, vp = xp * es, vm = xm * es;   // columns x, x+1, x-1
         const int pbytes = (int)(plane * es), rbytes = pitch * es;
         const bool dma_halo = DMA32 || (DMA16 && (nx % 2) == 0);
-        // DMA lanes: byte offset of halo column x0-2, x0-1, x0+BX, x0+BX+1
-        // (4-byte storage, lanes 0..3) or of the pairs (2-byte storage, lanes 0..1)
-        unsigned vh = 0;
-        if (tid < 4) {
-            int hc = DMA16 ? ((tid == 0) ? x0 - 2 : x0 + BX) : ((tid < 2) ? x0 - 2 + tid : x0 + BX + tid - 2);
-            hc %= nx;
-            if (hc < 0) hc += nx;
-            vh = (unsigned)hc * es;
+        // DMA lanes.  4-byte storage, lanes 0..3: halo column x0-2, x0-1,
+        // x0+BX, x0+BX+1 and its left and right neighbours (byte offsets).
+        // 2-byte storage, lanes 0..5: the pair starts x0-4, x0-2, x0,
+        // x0+BX-2, x0+BX, x0+BX+2.
+        auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
+        unsigned vh = 0, vhl = 0, vhr = 0;
+        if (tid < 6) {
+            const int hc = DMA16 ? ((tid < 3) ? x0 - 4 + 2 * tid : x0 + BX - 8 + 2 * tid)
+                                 : ((tid < 2) ? x0 - 2 + tid : x0 + BX + tid - 2);
+            vh = (unsigned)wrap(hc) * es;
+            vhl = (unsigned)wrap(hc - 1) * es;
+            vhr = (unsigned)wrap(hc + 1) * es;
         }
-        const int ndma = DMA16 ? 2 : 4;
+        const int ndma = DMA16 ? 6 : 4;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
         C4* halo = (C4*)dyn_lds;                                       // [(ly + 4) * 4]
@@ -299,13 +317,16 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         using R = Row<P>;
         // 18 deviations of row r (uniform across the block; mapped through the
         // walls or the periodic wrap) at column byte offset voff.
-        auto load = [&](R& fr, int r, unsigned voff) {
-            fr.load(rin0, rin1, voff + (unsigned)(map_row<P>(r, ny, walls) * rbytes), 0, pbytes);
+        auto load = [&](R& fr, int r) {
+            const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+            fr.load(rin0, rin1, vm + ro, vc + ro, vp + ro, 0, pbytes);
         };
-        // The same for a row that differs between lanes: the row goes into the
-        // per-lane offset and the SGPR offset keeps only the uniform plane.
-        auto load_lane = [&](R& fr, int r, unsigned voff) {
-            fr.load(rin0, rin1, voff + (unsigned)(map_row<P>(r, ny, walls) * rbytes), 0, pbytes);
+        // The same for a row and column that differ between lanes: both go into
+        // the per-lane offsets and the SGPR offset keeps only the uniform plane.
+        auto load_lane = [&](R& fr, int r, int col) {
+            const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+            fr.load(rin0, rin1, (unsigned)wrap(col - 1) * es + ro, (unsigned)col * es + ro,
+                    (unsigned)wrap(col + 1) * es + ro, 0, pbytes);
         };
         auto dens = [&](const R& fr, C& da, C& db) {
             da = fr[0];
@@ -320,11 +341,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             const int nh = (y1 - y0 + 4) * 4;
             for (int s = tid; s < nh; s += BX) {
                 const int c = s & 3, rr = s >> 2;
-                int hc = (c < 2) ? x0 - 2 + c : x0 + BX + c - 2;
-                hc %= nx;
-                if (hc < 0) hc += nx;
+                const int hc = wrap((c < 2) ? x0 - 2 + c : x0 + BX + c - 2);
                 R h;
-                load_lane(h, y0 - 2 + rr, (unsigned)hc * es);
+                load_lane(h, y0 - 2 + rr, hc);
                 C da, db;
                 dens(h, da, db);
                 C4 v;
@@ -341,23 +360,28 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         auto halo_fetch = [&](int r) {
             if constexpr (DMA32 || DMA16) {
                 if (dma_halo && tid < ndma) {
-                    const unsigned vo = vh + (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+                    const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
 #pragma unroll
-                    for (int q = 0; q < 18; ++q)
+                    for (int q = 0; q < 18; ++q) {
+                        const int cx = CX[q % 9];
+                        const unsigned vo = ro + ((DMA32 && cx > 0) ? vhl : ((DMA32 && cx < 0) ? vhr : vh));
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(
                             q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
                             __builtin_amdgcn_readfirstlane((q % 9) * pbytes), 0, 0);
+                    }
                 }
             }
         };
-        // Halo column value of plane q for lane tid (0..3) from the DMA ring.
+        // Plane q of halo column tid (0..3) from the DMA ring.  2-byte storage:
+        // the 12-element window row holds columns x0-4 .. x0+1 (elements 0..5)
+        // and x0+BX-2 .. x0+BX+3 (6..11); halo column tid under shift c_ix is
+        // element hb16 - c_ix (hb16: the unshifted element of the column).
+        const int hb16 = (tid < 2) ? 2 + tid : 6 + tid;
         auto hval = [&](int r, int q) -> C {
             if constexpr (DMA32) {
                 return (C)__builtin_bit_cast(float, hst[r & 3][q][tid]);
             } else if constexpr (DMA16) {
-                const unsigned wv = hst[r & 3][q][tid >> 1];
-                const unsigned short h = (unsigned short)((tid & 1) ? (wv >> 16) : (wv & 0xffffu));
-                return (C)__builtin_bit_cast(S, h);
+                return (C)__builtin_bit_cast(S, hst[r & 3][q][hb16 - CX[q % 9]]);
             } else {
                 return (C)0;
             }
@@ -463,7 +487,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             const bool bot = walls && (y == 0);
             const bool top = walls && (y == ny - 1);
             // byte offsets of the destination rows y-1, y, y+1 (periodic wrap in y;
-            // at a wall the row beyond it is never written)
+            // at a wall the row beyond it is never written).  The push is in y
+            // only: every store goes to the lane's own column, the x part of the
+            // move happens when the next step loads the shifted planes.
             const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
             const unsigned vrow_m = (unsigned)(ym * rbytes), vrow_0 = (unsigned)(y * rbytes),
                            vrow_p = (unsigned)(yp * rbytes);
@@ -493,31 +519,32 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                 if (!valid) return;
                 const rsrc_t ro = (s == 0) ? rout0 : rout1;
                 if (!(bot || top)) {
-                    // interior row: plain push to rows y-1, y, y+1 (periodic wrap)
+                    // interior row: push to rows y-1, y, y+1 (periodic wrap)
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
-                        const int cx = CX[i], cy = CY[i];
+                        const int cy = CY[i];
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
-                        st<P>(ro, vrow + vcol, i * pbytes, fs[i]);
+                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
                     }
                     return;
                 }
+                // wall row: a population leaving through the wall returns to this
+                // node as OPP[i]; in the shifted layout that slot is column x + c_ix
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     const int cx = CX[i], cy = CY[i];
+                    const unsigned vback = (cx == 0) ? vc : (cx > 0 ? vp : vm);
                     if (cy < 0 && bot) {
                         const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
-                        st<P>(ro, vrow_0 + vc, OPP[i] * pbytes, back);
+                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
                         if (cx != 0) mom_b += (C)cx * (fs[i] + back);
                     } else if (cy > 0 && top) {
                         const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
-                        st<P>(ro, vrow_0 + vc, OPP[i] * pbytes, back);
+                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
                         if (cx != 0) mom_t += (C)cx * (fs[i] + back);
                     } else {
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        const unsigned vcol = (cx == 0) ? vc : (cx > 0 ? vp : vm);
-                        st<P>(ro, vrow + vcol, i * pbytes, fs[i]);
+                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
                     }
                 }
             };
@@ -531,24 +558,24 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         // A row's halo loads are issued just before its own loads.
         R F0, F1, F2, F3;
         halo_fetch(y0 - 2);
-        load(F2, y0 - 2, vc);
+        load(F2, y0 - 2);
         halo_fetch(y0 - 1);
-        load(F3, y0 - 1, vc);
+        load(F3, y0 - 1);
         stage(F2, y0 - 2);
         stage(F3, y0 - 1);
         halo_fetch(y0);
-        load(F0, y0, vc);
+        load(F0, y0);
         halo_fetch(y0 + 1);
-        load(F1, y0 + 1, vc);
+        load(F1, y0 + 1);
         halo_fetch(y0 + 2);
-        load(F2, y0 + 2, vc);
+        load(F2, y0 + 2);
         stage(F0, y0);
         stage(F1, y0 + 1);
         auto iter = [&](int y, const R& fc, const R& fs2, R& fl) {
             stage(fs2, y + 2);
             if (y + 3 <= y1 + 1) {
                 halo_fetch(y + 3);
-                load(fl, y + 3, vc);
+                load(fl, y + 3);
             }
             lds_barrier();
             collide(fc, y);
@@ -583,6 +610,15 @@ __device__ __forceinline__ double decode(const typename P::S* p, const LatDesc& 
     return d.wref[q] + (double)*p;
 }
 
+// Column holding population q of the node in column x: each plane is stored
+// shifted in x by its direction's c_ix (periodic), the layout the step kernel
+// reads (it pulls in x and pushes in y).
+__device__ __forceinline__ int col_of(int x, int q, int nx)
+{
+    const int c = x - CX[q % 9];
+    return c < 0 ? c + nx : (c >= nx ? c - nx : c);
+}
+
 // f_is(r, 0) = f^eq_i(rho_s(r), u(r)), evaluated in FP64 and rounded once to
 // the storage format.
 template <class P>
@@ -601,13 +637,13 @@ __global__ void k_init(char* __restrict__ base, const LatDesc* __restrict__ dd, 
         const int y = (int)(k / d.nx), x = (int)(k % d.nx);
         const double u = ux ? ux[k] : 0.0, v = uy ? uy[k] : 0.0;
         const double uu = u * u + v * v;
-        S* out = f + (long long)y * d.pitch + x;
+        S* out = f + (long long)y * d.pitch;
         for (int s = 0; s < 2; ++s) {
             const double rho = s == 0 ? ra[k] : rb[k];
             for (int i = 0; i < 9; ++i) {
                 const double cu = CX[i] * u + CY[i] * v;
                 const double feq = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-                out[(9 * s + i) * d.plane] = (S)(C)(feq - d.wref[9 * s + i]);
+                out[(9 * s + i) * d.plane + col_of(x, i, d.nx)] = (S)(C)(feq - d.wref[9 * s + i]);
             }
         }
     }
@@ -626,11 +662,11 @@ __global__ void k_fields(char* __restrict__ base, const LatDesc* __restrict__ dd
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
          k += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(k / d.nx), x = (int)(k % d.nx);
-        const S* in = f + (long long)y * d.pitch + x;
+        const S* in = f + (long long)y * d.pitch;
         double rho[2] = {0, 0}, jx = 0, jy = 0;
         for (int s = 0; s < 2; ++s)
             for (int i = 0; i < 9; ++i) {
-                const double v = decode<P>(in + (9 * s + i) * d.plane, d, 9 * s + i);
+                const double v = decode<P>(in + (9 * s + i) * d.plane + col_of(x, i, d.nx), d, 9 * s + i);
                 rho[s] += v;
                 jx += v * CX[i];
                 jy += v * CY[i];
@@ -653,7 +689,7 @@ __global__ void k_export(char* __restrict__ base, const LatDesc* __restrict__ dd
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
          k += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(k / d.nx), x = (int)(k % d.nx);
-        out[k] = decode<P>(f + (long long)y * d.pitch + x + q * d.plane, d, q);
+        out[k] = decode<P>(f + (long long)y * d.pitch + col_of(x, q, d.nx) + q * d.plane, d, q);
     }
 }
 
@@ -673,11 +709,11 @@ k_sums(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, double*
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
          k += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(k / d.nx), x = (int)(k % d.nx);
-        const S* in = f + (long long)y * d.pitch + x;
+        const S* in = f + (long long)y * d.pitch;
         double rho[2] = {0, 0};
         for (int s = 0; s < 2; ++s)
             for (int i = 0; i < 9; ++i) {
-                const double v = decode<P>(in + (9 * s + i) * d.plane, d, 9 * s + i);
+                const double v = decode<P>(in + (9 * s + i) * d.plane + col_of(x, i, d.nx), d, 9 * s + i);
                 rho[s] += v;
                 acc[2] += v * CX[i];
                 acc[3] += v * CY[i];
