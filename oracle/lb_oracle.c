@@ -19,6 +19,9 @@
  *                    the two force definitions after it)
  *   4. collision     f*_is = f_is - (f_is - f^eq_is(rho_s, u + tau F_s/rho_s))/tau
  *                    (Eq. (1), right-hand side, with the quadratic equilibrium)
+ *                    where F_s also carries the species' share of the external
+ *                    body force of the paper's driving, F_x(y) = F0 sin(k_f y)
+ *                    (section "Numerical Results")
  *   5. streaming     f_is(r + c_i, t+1) = f*_is(r, t)             (Eq. (1), left)
  *
  * Readings of points the paper leaves open (each is listed with its reason in
@@ -34,7 +37,11 @@
  *   - walls (optional): half-way bounce-back at y = -1/2 and y = NY - 1/2 moving
  *     at u_bot, u_top along x, with the node's own pre-collision density in
  *     the moving-wall term; psi and rho beyond a wall are the even mirror of
- *     the fluid rows (row -1 <- row 0, row -2 <- row 1).
+ *     the fluid rows (row -1 <- row 0, row -2 <- row 1);
+ *   - the external body force acts on the fluid as a whole and is shared
+ *     between the species in proportion to their density,
+ *     F_ext,s = (rho_s / (rho_A + rho_B)) F0 sin(k_f y), so that both
+ *     species receive the same acceleration; y is the node's row index.
  *
  * Layout of a population array: f[((s*9 + i)*ny + y)*nx + x], s = 0 (A), 1 (B).
  * D2Q9 order: 0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
@@ -53,6 +60,7 @@ typedef struct {
     double g_rep[2];    /* G^r_AA, G^r_BB: belts 1-2, two-belt weights */
     double g_ab;        /* G^X_AB = G^X_BA: belt 1, D2Q9 weights, acts on rho */
     double u_top, u_bot;/* wall velocities along x */
+    double fx_amp, fx_k;/* body force F_x(y) = fx_amp sin(fx_k y); 0 = none */
 } orc_params;
 
 /* ---- lattice tables ---------------------------------------------------- */
@@ -258,9 +266,11 @@ void orc_collide(const orc_params* p, const double* f, double* fstar,
 #pragma omp parallel for schedule(static)
     for (long long kk = 0; kk < (long long)n; ++kk) {
         size_t k = (size_t)kk;
+        double fext = p->fx_amp * sin(p->fx_k * (double)(k / (size_t)nx));
         for (int s = 0; s < 2; ++s) {
             double rs = (s == 0) ? rho_a[k] : rho_b[k];
-            double vx = ux[k] + p->tau * F[2 * s][k] / rs;
+            double fsx = F[2 * s][k] + fext * rs / (rho_a[k] + rho_b[k]);
+            double vx = ux[k] + p->tau * fsx / rs;
             double vy = uy[k] + p->tau * F[2 * s + 1][k] / rs;
             double feq[9];
             orc_equilibrium(rs, vx, vy, feq);

@@ -25,6 +25,7 @@ class _Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
         ("g_att", ctypes.c_double * 2), ("g_rep", ctypes.c_double * 2),
         ("g_ab", ctypes.c_double), ("u_top", ctypes.c_double), ("u_bot", ctypes.c_double),
+        ("fx_amp", ctypes.c_double), ("fx_k", ctypes.c_double),
     ]
 
 
@@ -43,6 +44,8 @@ class OracleParams:
     walls: bool = True
     u_top: float = 0.0
     u_bot: float = 0.0
+    fx_amp: float = 0.0   # body force F_x(y) = fx_amp sin(fx_k y) (section "Numerical Results")
+    fx_k: float = 0.0
 
     def _c(self):
         p = _Params()
@@ -51,6 +54,7 @@ class OracleParams:
         p.g_att[0], p.g_att[1] = self.g_aa1, self.g_bb1
         p.g_rep[0], p.g_rep[1] = self.g_aa2, self.g_bb2
         p.g_ab, p.u_top, p.u_bot = self.g_ab, self.u_top, self.u_bot
+        p.fx_amp, p.fx_k = self.fx_amp, self.fx_k
         return p
 
 
