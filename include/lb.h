@@ -85,6 +85,11 @@ typedef struct {
                                     the initial density of that species */
     int32_t profile;      /* 1: accumulate the line-averaged u_x(y) every step */
     int32_t reserved;
+    double fx_amp;        /* external body force along x per site, F_x(y) = fx_amp sin(fx_k y) with
+                             y the row index (the driving of section "Numerical Results"); it is
+                             shared between the species in proportion to their density, so both
+                             receive the acceleration F_x / (rho_A + rho_B); 0 = none */
+    double fx_k;          /* wavenumber of the body force (2 pi / L in the paper's protocol) */
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -125,6 +130,13 @@ lb_status lb_populations(lb_handle* h, double* f);
  * per-step sums are accumulated in FP64 on the device.  Synchronises. */
 lb_status lb_stress(lb_handle* h, double* sig_bot, double* sig_top, int64_t* nsamples);
 lb_status lb_stress_reset(lb_handle* h);
+
+/* Instantaneous line-averaged speed U_x(y, t) = (1/nx) sum_x u_x(x, y, t) of the
+ * current populations, u the barycentric velocity (section "Numerical
+ * Results": the profile whose sine transform is the response R(t)).  FP64 on
+ * the device; prof: host array of ny doubles.  Leaves the time-averaging
+ * accumulators alone.  Synchronises. */
+lb_status lb_line_profile(lb_handle* h, double* prof);
 
 /* Time average of U_x(y) = (1/nx) sum_x u_x(x, y) over the same window as
  * lb_stress (requires p->profile = 1).  prof: host array of ny doubles.  The
@@ -202,6 +214,7 @@ lb_status lbb_stress_reset(lbb_handle* h);
 /* Lattice k's fields / profile, as lb_fields / lb_profile. */
 lb_status lbb_fields(lbb_handle* h, int32_t k, double* rho_a, double* rho_b, double* ux, double* uy);
 lb_status lbb_profile(lbb_handle* h, int32_t k, double* prof, int64_t* nsamples);
+lb_status lbb_line_profile(lbb_handle* h, int32_t k, double* prof);
 /* Launch shape (as lb_set_launch) and grid size (0 = one block per tile,
  * > 0 = persistent grid of that many blocks). */
 lb_status lbb_set_launch(lbb_handle* h, int32_t bx, int32_t ly, int32_t grid);

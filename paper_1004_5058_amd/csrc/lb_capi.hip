@@ -70,9 +70,10 @@ lb_status validate(const lb_params* p, int storage0)
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LB_EINVAL, "rho0 must be > 0");
     const double g[] = {p->g_aa1, p->g_aa2, p->g_bb1, p->g_bb2, p->g_ab, p->u_top, p->u_bot,
-                        p->rho_ref_a, p->rho_ref_b};
+                        p->rho_ref_a, p->rho_ref_b, p->fx_amp, p->fx_k};
     for (double v : g)
-        if (!std::isfinite(v)) return fail(LB_EINVAL, "non-finite coupling, wall speed or reference density");
+        if (!std::isfinite(v))
+            return fail(LB_EINVAL, "non-finite coupling, wall speed, reference density or body force");
     if (p->walls_y != 0 && p->walls_y != 1) return fail(LB_EINVAL, "walls_y must be 0 or 1");
     // byte offsets inside one species' planes must fit the 32-bit buffer offset
     const size_t es = storage_size(p->storage);
@@ -86,11 +87,12 @@ struct Lat {
     lb_params p;
     int pitch = 0, ngroups = 0;
     long long plane = 0;
-    size_t off_f[2] = {0, 0}, off_stress = 0, off_prof = 0, end = 0;
+    size_t off_f[2] = {0, 0}, off_stress = 0, off_prof = 0, off_body = 0, end = 0;
     double rho_ref[2] = {0, 0};
 };
 
-// Layout: [descs][partials][results] then per lattice [f0][f1][stress][prof].
+// Layout: [descs][partials][results][item table] then per lattice
+// [f0][f1][stress][prof][body force per row].
 struct Layout {
     size_t off_desc = 0, off_part = 0, off_res = 0, off_tiles = 0, total = 0;
     int max_items = 0;   // capacity of the item -> lattice table (any launch shape)
@@ -122,7 +124,9 @@ Layout plan(std::vector<Lat>& lats)
         a.off_stress = off + 2 * fbytes;
         a.off_prof = a.off_stress + align_up(sizeof(double) * 2 * a.p.nx, ALIGN);
         const size_t pbytes = a.p.profile ? align_up(sizeof(double) * (size_t)a.ngroups * a.p.ny, ALIGN) : 0;
-        a.end = a.off_prof + pbytes;
+        a.off_body = a.off_prof + pbytes;
+        const size_t bbytes = a.p.fx_amp != 0.0 ? align_up(sizeof(double) * (size_t)a.p.ny, ALIGN) : 0;
+        a.end = a.off_body + bbytes;
         off = a.end;
     }
     L.total = off;
@@ -137,6 +141,7 @@ void fill_desc(const Lat& a, lbk::LatDesc& d)
     d.off_f[1] = (long long)a.off_f[1];
     d.off_stress = (long long)a.off_stress;
     d.off_prof = p.profile ? (long long)a.off_prof : -1;
+    d.off_body = p.fx_amp != 0.0 ? (long long)a.off_body : -1;
     d.plane = a.plane;
     d.nx = p.nx;
     d.ny = p.ny;
@@ -430,6 +435,17 @@ lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t
                                         dst[2], dst[3], h->stream);
         if (e != hipSuccess) { delete h; return fail(LB_EDEVICE, "init launch failed: %s", hipGetErrorString(e)); }
     }
+    // body force of each row, F_x(y) = fx_amp sin(fx_k y), evaluated in FP64 on the host
+    std::vector<std::vector<double>> body(n);
+    for (int k = 0; k < n; ++k) {
+        const Lat& a = h->lats[k];
+        if (a.p.fx_amp == 0.0) continue;
+        body[k].resize(a.p.ny);
+        for (int y = 0; y < a.p.ny; ++y) body[k][y] = a.p.fx_amp * std::sin(a.p.fx_k * (double)y);
+        hipError_t e = hipMemcpyAsync(h->base + a.off_body, body[k].data(), sizeof(double) * a.p.ny,
+                                      hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) { delete h; return fail(LB_EDEVICE, "upload failed: %s", hipGetErrorString(e)); }
+    }
     HIP_TRY(lbk::launch_fill((double*)(h->base + lay.off_res), 8 + 2 * n, 0.0, h->stream));
     st = reset_acc(h);
     if (st != LB_OK) { delete h; return st; }
@@ -495,6 +511,19 @@ lb_status profile_one(lbb_handle* h, int k, double* prof, int64_t* ns)
     const double m = h->nsamples > 0 ? (double)h->nsamples * a.p.nx : 1.0;
     for (int y = 0; y < a.p.ny; ++y) prof[y] = h->nsamples > 0 ? prof[y] / m : 0.0;
     if (ns) *ns = h->nsamples;
+    return LB_OK;
+}
+
+// Instantaneous line-averaged u_x of lattice k, staged in its idle population buffer.
+lb_status line_profile(lbb_handle* h, int k, double* prof)
+{
+    if (k < 0 || k >= (int)h->lats.size()) return fail(LB_EINVAL, "lattice index out of range");
+    if (!prof) return fail(LB_EINVAL, "null profile array");
+    const Lat& a = h->lats[k];
+    double* stg = (double*)(h->base + a.off_f[h->cur ^ 1]);
+    HIP_TRY(lbk::launch_line_profile(h->storage, h->base, h->d_desc() + k, a.p.ny, h->cur, stg, h->stream));
+    HIP_TRY(hipMemcpyAsync(prof, stg, sizeof(double) * a.p.ny, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     return LB_OK;
 }
 
@@ -855,6 +884,12 @@ lb_status lb_profile(lb_handle* h, double* prof, int64_t* ns)
     return profile_one(&h->b, 0, prof, ns);
 }
 
+lb_status lb_line_profile(lb_handle* h, double* prof)
+{
+    CHECK_H(h);
+    return line_profile(&h->b, 0, prof);
+}
+
 lb_status lb_sums(lb_handle* h, double out[5])
 {
     CHECK_H(h);
@@ -1037,6 +1072,12 @@ lb_status lbb_profile(lbb_handle* h, int32_t k, double* prof, int64_t* ns)
 {
     CHECK_H(h);
     return profile_one(h, k, prof, ns);
+}
+
+lb_status lbb_line_profile(lbb_handle* h, int32_t k, double* prof)
+{
+    CHECK_H(h);
+    return line_profile(h, k, prof);
 }
 
 lb_status lbb_set_launch(lbb_handle* h, int32_t bx, int32_t ly, int32_t grid)

@@ -13,6 +13,7 @@ struct LatDesc {
                            // layout [s][i][y][pitch]
     long long off_stress;  // [2][nx] FP64: x momentum received by bottom / top wall, summed over steps
     long long off_prof;    // [ngroups][ny] FP64: sum over steps of per-64-column sums of u_x; < 0: off
+    long long off_body;    // [ny] FP64: external body force F_x(y) of each row; < 0: none
     long long plane;       // elements per (species, direction) plane = ny * pitch
     int nx, ny, pitch, walls;
     int item_begin;        // first global work item of this lattice (multiple of 8)

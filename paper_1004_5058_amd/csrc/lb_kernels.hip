@@ -308,6 +308,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const int ndma = DMA16 ? 6 : 4;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
+        const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
         C4* halo = (C4*)dyn_lds;                                       // [(ly + 4) * 4]
         double* profS = (double*)(dyn_lds + sizeof(C4) * 4 * (d.ly + 4)); // [BX/64][ly]
         C mom_b = 0, mom_t = 0;   // wall momentum of this thread's column, summed over the segment
@@ -477,6 +478,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                        + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
             const C inv_rho = rcp(ra + rb);
             const C ux = jx * inv_rho, uy = jy * inv_rho;
+            // external body force of the row, shared by density: the same
+            // acceleration F_x(y) / (rho_A + rho_B) for both species
+            const C gx = (body != nullptr) ? (C)body[y] * inv_rho : (C)0;
 
             if (prof != nullptr && x0 + 64 * wave < nx) {    // wave-uniform condition
                 double su = valid ? (double)ux : 0.0;
@@ -498,7 +502,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             // then the push of species s to the neighbours (bounce-back at walls).
             auto relax_push = [&](int s, C rs, C drs, C Fx, C Fy) {
                 const C inv = rcp(rs);
-                const C vx = ux + tau * Fx * inv;
+                const C vx = ux + tau * (Fx * inv + gx);
                 const C vy = uy + tau * Fy * inv;
                 const C usq = (C)1.5 * (vx * vx + vy * vy);
                 const C r0 = rs * (C)(4.0 / 9.0), r1 = rs * (C)(1.0 / 9.0), r2 = rs * (C)(1.0 / 36.0);
@@ -752,6 +756,32 @@ k_sums_final(const double* __restrict__ partials, int nparts, double* __restrict
     }
 }
 
+// out[y] = (1/nx) sum_x u_x(x, y) of the stored populations, FP64; one block per row.
+template <class P>
+__global__ void __launch_bounds__(256)
+k_line_profile(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, double* __restrict__ out)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const int y = blockIdx.x;
+    const S* f = (const S*)(base + d.off_f[buf]) + (long long)y * d.pitch;
+    double acc = 0;
+    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
+        double rho = 0, jx = 0;
+        for (int q = 0; q < 18; ++q) {
+            const double v = decode<P>(f + q * d.plane + col_of(x, q, d.nx), d, q);
+            rho += v;
+            jx += v * CX[q % 9];
+        }
+        acc += jx / rho;
+    }
+    __shared__ double red[4];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[y] = (red[0] + red[1] + red[2] + red[3]) / d.nx;
+}
+
 // Per lattice k: out[2k] = sum_x bottom accumulator, out[2k+1] = sum_x top.
 __global__ void __launch_bounds__(256)
 k_stress_reduce(char* __restrict__ base, const LatDesc* __restrict__ descs, double* __restrict__ out)
@@ -908,6 +938,19 @@ hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int n
                        double* partials, double* out, int* flag, hipStream_t s)
 {
     LBK_DISPATCH(storage, (sums_p<P>(base, d, buf, nblocks, partials, out, flag, s)));
+}
+
+template <class P>
+static hipError_t line_profile_p(char* base, const LatDesc* desc, int ny, int buf, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_line_profile<P>, dim3(ny), dim3(256), 0, s, base, desc, buf, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_profile(int storage, char* base, const LatDesc* desc, int ny, int buf, double* out,
+                               hipStream_t s)
+{
+    LBK_DISPATCH(storage, (line_profile_p<P>(base, desc, ny, buf, out, s)));
 }
 
 hipError_t launch_stress_reduce(char* base, const LatDesc* descs, int nlat, double* out, hipStream_t s)

@@ -19,6 +19,8 @@ hipError_t launch_export(int storage, char* base, const LatDesc* d, long long ns
                          int q, double* out, hipStream_t s);
 hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int nblocks,
                        double* partials, double* out, int* flag, hipStream_t s);
+hipError_t launch_line_profile(int storage, char* base, const LatDesc* desc, int ny, int buf, double* out,
+                               hipStream_t s);
 hipError_t launch_stress_reduce(char* base, const LatDesc* descs, int nlat, double* out, hipStream_t s);
 hipError_t launch_profile_reduce(char* base, const LatDesc* d, int ny, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);

@@ -37,6 +37,7 @@ class lb_params(ctypes.Structure):
         ("u_top", ctypes.c_double), ("u_bot", ctypes.c_double),
         ("rho_ref_a", ctypes.c_double), ("rho_ref_b", ctypes.c_double),
         ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("fx_amp", ctypes.c_double), ("fx_k", ctypes.c_double),
     ]
 
 
@@ -130,7 +131,7 @@ def _field(a, shape):
 
 def make_params(nx, ny, *, tau=1.0, rho0=0.83, g_aa1=-9.0, g_aa2=8.1, g_bb1=-9.0, g_bb2=8.1,
                 g_ab=0.405, walls=True, u_top=0.0, u_bot=0.0, storage="f32", rho_ref_a=0.0,
-                rho_ref_b=0.0, profile=False):
+                rho_ref_b=0.0, profile=False, fx_amp=0.0, fx_k=0.0):
     p = lb_params()
     p.nx, p.ny, p.walls_y = int(nx), int(ny), int(bool(walls))
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -139,6 +140,7 @@ def make_params(nx, ny, *, tau=1.0, rho0=0.83, g_aa1=-9.0, g_aa2=8.1, g_bb1=-9.0
     p.u_top, p.u_bot = u_top, u_bot
     p.rho_ref_a, p.rho_ref_b = rho_ref_a, rho_ref_b
     p.profile = int(bool(profile))
+    p.fx_amp, p.fx_k = fx_amp, fx_k
     return p
 
 
@@ -275,6 +277,12 @@ class Lattice:
     def profile(self):
         return lb_profile(self._h, self.ny)
 
+    def line_profile(self):
+        """Instantaneous U_x(y) = (1/nx) sum_x u_x of the current state."""
+        out = np.empty(self.ny)
+        _check(_lib.lb_line_profile(self._h, _dptr(out)))
+        return out
+
     def sums(self):
         return lb_sums(self._h)
 
@@ -391,6 +399,12 @@ class Batch:
         ns = ctypes.c_int64()
         _check(_lib.lbb_profile(self._h, int(k), _dptr(prof), ctypes.byref(ns)))
         return prof, ns.value
+
+    def line_profile(self, k):
+        ny, _ = self.shapes[k]
+        out = np.empty(ny)
+        _check(_lib.lbb_line_profile(self._h, int(k), _dptr(out)))
+        return out
 
     def set_launch(self, bx=0, ly=0, grid=0):
         _check(_lib.lbb_set_launch(self._h, int(bx), int(ly), int(grid)))
