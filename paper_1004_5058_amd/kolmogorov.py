@@ -65,9 +65,15 @@ def scatter(profile, F0):
     return np.abs(shear_profile(U)), np.abs(stress_profile(F0, U.size))
 
 
-def initial_densities(L, nx=None):
-    """The paper's start: rho_A = 0.61 (1 + 0.1 sin(k_in y)), rho_B = 0.61 (1 + 0.01 sin(k_in y))."""
+def initial_densities(L, nx=None, init="paper", seed=1):
+    """init = "paper": the paper's start, rho_A = 0.61 (1 + 0.1 sin(k_in y)),
+    rho_B = 0.61 (1 + 0.01 sin(k_in y)); "emulsion": the seeded demixed start
+    of the sheared workloads (per site (1.0, 0.1) or (0.1, 1.0))."""
     nx = L if nx is None else nx
+    if init == "emulsion":
+        return inputs.emulsion(nx, L, seed=seed)
+    if init != "paper":
+        raise ValueError(f"unknown start {init!r}")
     k_in = 64.0 * np.pi / L
     return inputs.sinusoid_y(nx, L, 0.61, 0.1, k_in), inputs.sinusoid_y(nx, L, 0.61, 0.01, k_in)
 
@@ -80,15 +86,15 @@ def lattice_kwargs(L, rho0, U0, couplings=None, rho=1.22):
 
 
 def run(L=512, rho0=0.83, U0=0.1, steps=100000, sample_every=1000, average_from=None, storage="f32",
-        couplings=None, device="cuda:0", log=None):
+        couplings=None, device="cuda:0", init="paper", log=None):
     """Run the protocol on one lattice.  Returns R(t) samples, the profile
     averaged over [average_from, steps), the stress/shear scatter and its
     Herschel-Bulkley fit (None when fewer than three flowing points)."""
     from . import lb
     if average_from is None:
         average_from = steps // 2
-    ra, rb = initial_densities(L)
-    kw = lattice_kwargs(L, rho0, U0, couplings)
+    ra, rb = initial_densities(L, init=init)
+    kw = lattice_kwargs(L, rho0, U0, couplings, rho=float(np.mean(ra + rb)))
     F0 = kw["fx_amp"]
     lat = lb.Lattice(L, L, ra, rb, None, None, device=device, storage=storage, profile=True, **kw)
     t0 = time.perf_counter()
@@ -124,3 +130,94 @@ def run(L=512, rho0=0.83, U0=0.1, steps=100000, sample_every=1000, average_from=
     return dict(L=L, rho0=rho0, U0=U0, F0=F0, steps=steps, t=np.array(ts), R=np.array(Rs), profile=prof,
                 samples=nsamp, R_mean=response(prof, U0) if nsamp else float("nan"), S=S, sigma=P,
                 sigma0=F0 / wavenumber(L), fit=fit, wall_s=wall, mlups=L * L * steps / wall * 1e-6)
+
+
+def sweep(rho0_list, L=512, U0=0.1, steps=100000, sample_every=1000, average_from=None, storage="f32",
+          couplings=None, device="cuda:0", tune=True, init="paper", log=None):
+    """The protocol at several rho0 at once: one lattice per rho0 in one batch
+    (one launch per step for all of them).  Returns one result dict per rho0
+    (as `run`) plus the batch's wall time."""
+    from . import lb
+    if average_from is None:
+        average_from = steps // 2
+    ra, rb = initial_densities(L, init=init)
+    kws = [lattice_kwargs(L, r0, U0, couplings, rho=float(np.mean(ra + rb))) for r0 in rho0_list]
+    specs = [dict(nx=L, ny=L, rho_a=ra, rho_b=rb, ux=None, uy=None, **kw) for kw in kws]
+    b = lb.Batch(specs, device=device, storage=storage, profile=True)
+    if tune:
+        b.autotune(None, steps=5)
+    t0 = time.perf_counter()
+    n = len(specs)
+    ts, Rs = [], [[] for _ in range(n)]
+    t = 0
+    averaging = False
+    while t < steps:
+        if not averaging and t >= average_from:
+            b.stress_reset()
+            averaging = True
+        m = min(sample_every, steps - t)
+        if not averaging:
+            m = min(m, average_from - t)
+        b.step(m)
+        t += m
+        ts.append(t)
+        for k in range(n):
+            Rs[k].append(response(b.line_profile(k), U0))
+        if log:
+            log(f"t={t} R=" + " ".join(f"{R[-1]:.4f}" for R in Rs))
+    if not averaging:
+        b.stress_reset()
+    wall = time.perf_counter() - t0
+    out = []
+    for k, (r0, kw) in enumerate(zip(rho0_list, kws)):
+        prof, nsamp = b.profile(k)
+        F0 = kw["fx_amp"]
+        S, P = scatter(prof, F0)
+        flowing = S > 1e-3 * max(S.max(), 1e-300)
+        fit = None
+        if np.count_nonzero(flowing) >= 3:
+            try:
+                fit = flowcurve.hb_fit(S[flowing], P[flowing])
+            except ValueError:
+                fit = None
+        out.append(dict(L=L, rho0=r0, U0=U0, F0=F0, steps=steps, t=np.array(ts), R=np.array(Rs[k]),
+                        profile=prof, samples=nsamp, R_mean=response(prof, U0) if nsamp else float("nan"),
+                        S=S, sigma=P, sigma0=F0 / wavenumber(L), fit=fit))
+    b.close()
+    return out, wall
+
+
+def vft_fit(rho0, inv_R, rho_c_grid=None):
+    """Fit 1/R = A exp(B / (rho_c - rho0)) (section "Numerical Results", Fig. 5):
+    for each rho_c above the data, ln(1/R) is linear in 1/(rho_c - rho0), so
+    (ln A, B) is a linear least-squares solve; the best rho_c on the grid is
+    then refined by golden-section search.  Returns dict(A, B, rho_c, rss)."""
+    x = np.asarray(rho0, dtype=np.float64)
+    z = np.log(np.asarray(inv_R, dtype=np.float64))
+    if x.size < 3:
+        raise ValueError("need at least three points")
+    lo = x.max() + 1e-6
+    if rho_c_grid is None:
+        rho_c_grid = lo + np.logspace(-5, 0, 400)
+
+    def solve(rc):
+        A = np.column_stack([np.ones_like(x), 1.0 / (rc - x)])
+        coef, *_ = np.linalg.lstsq(A, z, rcond=None)
+        r = z - A @ coef
+        return float(r @ r), coef
+
+    best = min(rho_c_grid, key=lambda rc: solve(rc)[0])
+    i = int(np.searchsorted(rho_c_grid, best))
+    a = rho_c_grid[max(i - 1, 0)]
+    b = rho_c_grid[min(i + 1, len(rho_c_grid) - 1)]
+    g = (np.sqrt(5.0) - 1.0) / 2.0
+    c, d = b - g * (b - a), a + g * (b - a)
+    for _ in range(200):
+        if solve(c)[0] < solve(d)[0]:
+            b = d
+        else:
+            a = c
+        c, d = b - g * (b - a), a + g * (b - a)
+    rc = 0.5 * (a + b)
+    rss, coef = solve(rc)
+    return dict(A=float(np.exp(coef[0])), B=float(coef[1]), rho_c=float(rc), rss=rss)

@@ -115,3 +115,16 @@ def test_paper_start_and_couplings():
     assert ra.shape == (512, 512)
     assert ra.max() == pytest.approx(0.61 * 1.1, rel=1e-12) and rb.max() == pytest.approx(0.61 * 1.01, rel=1e-12)
     assert K.PAPER_COUPLINGS == dict(tau=1.0, g_aa1=-9.0, g_aa2=8.1, g_bb1=-8.0, g_bb2=7.1, g_ab=0.045)
+
+
+def test_vft_fit_recovers_the_papers_parameters():
+    """1/R = A exp(B/(rho_c - rho0)) with the printed A = 3.51, B = 0.045,
+    rho_c = 0.867 over the paper's rho0 range is recovered exactly."""
+    rho0 = np.array([0.70, 0.75, 0.78, 0.80, 0.81, 0.83, 0.85, 0.86])
+    inv_R = 3.51 * np.exp(0.045 / (0.867 - rho0))
+    fit = K.vft_fit(rho0, inv_R)
+    assert fit["rho_c"] == pytest.approx(0.867, abs=1e-6)
+    assert fit["A"] == pytest.approx(3.51, rel=1e-4)
+    assert fit["B"] == pytest.approx(0.045, rel=1e-4)
+    with pytest.raises(ValueError):
+        K.vft_fit([0.7, 0.8], [1.0, 2.0])
