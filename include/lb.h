@@ -69,7 +69,7 @@ typedef enum {
  * (density deviations, deviations of psi from psi(rho_ref)), so the rounding
  * error scales with the departure from the reference state rather than with
  * f itself.  Arithmetic is FP64 for LB_F64 and FP32 otherwise. */
-typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3 } lb_storage;
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3, LB_MOM32 = 4, LB_MOM64 = 5 } lb_storage;
 
 typedef struct {
     int32_t nx, ny;       /* lattice sites along x (periodic) and y; 1 <= nx, 2 <= ny */

@@ -50,9 +50,18 @@ size_t storage_size(int storage)
     case LB_F32: return 4;
     case LB_F16DEV: return 2;
     case LB_BF16DEV: return 2;
+    case LB_MOM32: return 4;
+    case LB_MOM64: return 8;
     default: return 0;
     }
 }
+
+// Bytes per site of FP64 staging a state buffer must hold (four arrays).
+constexpr size_t STAGE_BYTES_PER_SITE = 4 * sizeof(double);
+
+// Values stored per site: 18 populations, or the 6 moments of the tau = 1 form.
+size_t planes_of(int storage) { return storage >= LB_MOM32 ? 6 : 18; }
+bool is_mom(int storage) { return storage >= LB_MOM32; }
 
 // Two-belt weights on |c|^2 = 1, 2, 4, 5, 8 and D2Q9 belt-1 weights.
 const double P12[5] = {4.0 / 63.0, 4.0 / 135.0, 1.0 / 180.0, 2.0 / 945.0, 1.0 / 15120.0};
@@ -64,7 +73,9 @@ lb_status validate(const lb_params* p, int storage0)
     if (!p) return fail(LB_EINVAL, "null parameters");
     if (p->nx < 1 || p->ny < 2) return fail(LB_EINVAL, "need nx >= 1 and ny >= 2 (got %d x %d)", p->nx, p->ny);
     if (p->nx > 65536 || p->ny > 65536) return fail(LB_EINVAL, "lattice side above 65536");
-    if (p->storage < 0 || p->storage > 3) return fail(LB_EINVAL, "unknown storage %d", p->storage);
+    if (p->storage < 0 || p->storage > 5) return fail(LB_EINVAL, "unknown storage %d", p->storage);
+    if (is_mom(p->storage) && p->tau != 1.0)
+        return fail(LB_EINVAL, "moment storage holds the post-collision state only at tau = 1 (got %g)", p->tau);
     if (storage0 >= 0 && p->storage != storage0)
         return fail(LB_EINVAL, "all lattices of a batch share one storage precision");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
@@ -78,8 +89,9 @@ lb_status validate(const lb_params* p, int storage0)
     // byte offsets inside one species' planes must fit the 32-bit buffer offset
     const size_t es = storage_size(p->storage);
     const size_t pitch = align_up((size_t)p->nx, 64);
-    if (9ull * pitch * p->ny * es >= (1ull << 32))
-        return fail(LB_EINVAL, "lattice too large: one species' populations exceed 4 GiB");
+    const size_t per = is_mom(p->storage) ? 6 : 9;   // values addressed through one buffer resource
+    if (per * pitch * p->ny * es >= (1ull << 32))
+        return fail(LB_EINVAL, "lattice too large: one buffer resource would exceed 4 GiB");
     return LB_OK;
 }
 
@@ -118,7 +130,11 @@ Layout plan(std::vector<Lat>& lats)
         a.pitch = (int)align_up((size_t)a.p.nx, 64);
         a.plane = (long long)a.pitch * a.p.ny;
         a.ngroups = (a.p.nx + 63) / 64;
-        const size_t fbytes = align_up(18ull * a.plane * es, ALIGN);
+        // Each state buffer also serves as staging for four FP64 arrays of
+        // nx*ny values (initial fields, field reads): at least 32 bytes per
+        // site, whatever the storage needs (6 FP32 moments need only 24).
+        const size_t per_site = std::max<size_t>(planes_of(a.p.storage) * es, STAGE_BYTES_PER_SITE);
+        const size_t fbytes = align_up(per_site * a.plane, ALIGN);
         a.off_f[0] = off;
         a.off_f[1] = off + fbytes;
         a.off_stress = off + 2 * fbytes;
@@ -220,6 +236,9 @@ struct lb_handle {
     lbb_handle b;
 };
 
+// The state is still the initial one (moment storage: not yet a streamed state).
+int first_state(const lbb_handle* h) { return (is_mom(h->storage) && h->t == 0) ? 1 : 0; }
+
 namespace {
 
 void drop_graphs(lbb_handle* h)
@@ -267,10 +286,10 @@ int launch_grid(const lbb_handle* h)
     return std::max(1, h->ntot);
 }
 
-lb_status launch_one(lbb_handle* h, hipStream_t s, int src)
+lb_status launch_one(lbb_handle* h, hipStream_t s, int src, int first = 0)
 {
     hipError_t e = lbk::launch_step(h->storage, h->bx, h->base, h->d_desc(), h->d_tiles(),
-                                    h->ntot, src, launch_grid(h), h->ly_max, s);
+                                    h->ntot, src, first, launch_grid(h), h->ly_max, s);
     if (e != hipSuccess) return fail(LB_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
     return LB_OK;
 }
@@ -299,7 +318,7 @@ lb_status run_sums(lbb_handle* h, int k, int* flag)
 {
     const Lat& a = h->lats[k];
     (void)a;
-    hipError_t e = lbk::launch_sums(h->storage, h->base, h->d_desc() + k, h->cur, lbk::sums_blocks(),
+    hipError_t e = lbk::launch_sums(h->storage, h->base, h->d_desc() + k, h->cur, first_state(h), lbk::sums_blocks(),
                                     h->d_part(), h->d_res(), flag, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "sums launch failed: %s", hipGetErrorString(e));
     return LB_OK;
@@ -308,6 +327,21 @@ lb_status run_sums(lbb_handle* h, int k, int* flag)
 lb_status steps(lbb_handle* h, int32_t n)
 {
     if (n < 0) return fail(LB_EINVAL, "negative step count");
+    if (n > 0 && first_state(h)) {
+        // the moment form's first step reads the initial local equilibria in
+        // place; it is launched on its own, never inside a graph
+        lb_status st = launch_one(h, h->stream, h->cur, 1);
+        if (st != LB_OK) return st;
+        h->cur ^= 1;
+        h->t += 1;
+        h->nsamples += 1;
+        n -= 1;
+        if (h->watchdog > 0 && h->t % h->watchdog == 0)
+            for (size_t k = 0; k < h->lats.size(); ++k) {
+                st = run_sums(h, (int)k, h->d_flag());
+                if (st != LB_OK) return st;
+            }
+    }
     while (n > 0) {
         int chunk = n;
         if (h->watchdog > 0) {
@@ -422,6 +456,10 @@ lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t
     for (int k = 0; k < n; ++k) {
         const Lat& a = h->lats[k];
         const size_t ns = (size_t)a.p.nx * a.p.ny;
+        if (ns * STAGE_BYTES_PER_SITE > a.off_f[1] - a.off_f[0]) {
+            delete h;
+            return fail(LB_EINVAL, "internal: staging does not fit the state buffer");
+        }
         double* stg = (double*)(h->base + a.off_f[1]);
         const double* src[4] = {ra[k], rb[k], ux ? ux[k] : nullptr, uy ? uy[k] : nullptr};
         double* dst[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -461,17 +499,19 @@ lb_status lattice_fields(lbb_handle* h, int k, double* ra, double* rb, double* u
     const Lat& a = h->lats[k];
     const size_t ns = (size_t)a.p.nx * a.p.ny;
     if (!host) {
-        HIP_TRY(lbk::launch_fields(h->storage, h->base, h->d_desc() + k, (long long)ns, h->cur, ra, rb, ux, uy,
-                                   h->stream));
+        HIP_TRY(lbk::launch_fields(h->storage, h->base, h->d_desc() + k, (long long)ns, h->cur, first_state(h), ra,
+                                   rb, ux, uy, h->stream));
         return LB_OK;
     }
-    // compute into the idle population buffer, then copy out
+    // compute into the idle state buffer, then copy out
+    if (ns * STAGE_BYTES_PER_SITE > a.off_f[1] - a.off_f[0])
+        return fail(LB_EINVAL, "internal: staging does not fit the state buffer");
     double* stg = (double*)(h->base + a.off_f[h->cur ^ 1]);
     double* outs[4] = {ra, rb, ux, uy};
     double* dev[4];
     for (int m = 0; m < 4; ++m) dev[m] = outs[m] ? stg + m * ns : nullptr;
-    HIP_TRY(lbk::launch_fields(h->storage, h->base, h->d_desc() + k, (long long)ns, h->cur, dev[0], dev[1],
-                               dev[2], dev[3], h->stream));
+    HIP_TRY(lbk::launch_fields(h->storage, h->base, h->d_desc() + k, (long long)ns, h->cur, first_state(h), dev[0],
+                               dev[1], dev[2], dev[3], h->stream));
     for (int m = 0; m < 4; ++m)
         if (outs[m]) HIP_TRY(hipMemcpyAsync(outs[m], dev[m], ns * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -521,7 +561,8 @@ lb_status line_profile(lbb_handle* h, int k, double* prof)
     if (!prof) return fail(LB_EINVAL, "null profile array");
     const Lat& a = h->lats[k];
     double* stg = (double*)(h->base + a.off_f[h->cur ^ 1]);
-    HIP_TRY(lbk::launch_line_profile(h->storage, h->base, h->d_desc() + k, a.p.ny, h->cur, stg, h->stream));
+    HIP_TRY(lbk::launch_line_profile(h->storage, h->base, h->d_desc() + k, a.p.ny, h->cur, first_state(h), stg,
+                                     h->stream));
     HIP_TRY(hipMemcpyAsync(prof, stg, sizeof(double) * a.p.ny, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LB_OK;
@@ -618,8 +659,8 @@ std::string arch_name()
 
 const char* storage_name(int s)
 {
-    static const char* n[] = {"f64", "f32", "f16dev", "bf16dev"};
-    return (s >= 0 && s < 4) ? n[s] : "unknown";
+    static const char* n[] = {"f64", "f32", "f16dev", "bf16dev", "mom32", "mom64"};
+    return (s >= 0 && s < 6) ? n[s] : "unknown";
 }
 
 std::string tune_key(const lbb_handle* h)
@@ -693,7 +734,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     std::vector<size_t> fb(h->lats.size()), ab(h->lats.size());
     for (size_t k = 0; k < h->lats.size(); ++k) {
         const Lat& a = h->lats[k];
-        fb[k] = 18ull * a.plane * storage_size(h->storage);
+        fb[k] = planes_of(h->storage) * a.plane * storage_size(h->storage);
         ab[k] = a.end - a.off_stress;
         total += fb[k] + ab[k];
     }
@@ -857,7 +898,8 @@ lb_status lb_populations(lb_handle* h, double* f)
     const size_t ns = (size_t)a.p.nx * a.p.ny;
     double* stg = (double*)(b->base + a.off_f[b->cur ^ 1]);
     for (int q = 0; q < 18; ++q) {
-        HIP_TRY(lbk::launch_export(b->storage, b->base, b->d_desc(), (long long)ns, b->cur, q, stg, b->stream));
+        HIP_TRY(lbk::launch_export(b->storage, b->base, b->d_desc(), (long long)ns, b->cur, first_state(b), q, stg,
+                                   b->stream));
         HIP_TRY(hipMemcpyAsync(f + q * ns, stg, ns * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     }
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -941,7 +983,7 @@ lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
     if (!bytes) return fail(LB_EINVAL, "null size");
     lbb_handle* b = &h->b;
     const Lat& a = b->lats[0];
-    const size_t fb = 18ull * a.plane * storage_size(b->storage);
+    const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
     const size_t sbb = 2ull * a.p.nx * sizeof(double);
     const size_t pb = a.p.profile ? (size_t)a.ngroups * a.p.ny * sizeof(double) : 0;
     const size_t need = sizeof(CkptHeader) + fb + sbb + pb;

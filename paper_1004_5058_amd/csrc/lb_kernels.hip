@@ -836,6 +836,534 @@ k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n)
         dst[k] = src[k];
 }
 
+// ------------------------------------------------------------ moment form ---
+//
+// At tau = 1 the BGK collision of Eq. (1) replaces every population by the
+// equilibrium at the shifted velocity, f*_is = f^eq_i(rho_s, v_s), so the
+// post-collision state of a site is the six numbers (rho_s, v_s) of the two
+// species.  The moment form stores them instead of the 18 populations and
+// rebuilds each incoming population from its source site,
+//   f_is(x, t) = f^eq_i(rho_s, v_s)(x - c_i, t - 1),
+// or, across a wall, from the bounced population of the site itself.  It is
+// the same recurrence as the population form at tau = 1 and moves 6 loads and
+// 6 stores per site instead of 36.
+//
+// Planes, each [y][pitch]: 0, 1 = rho_A - rho_ref_A, rho_B - rho_ref_B;
+// 2, 3 = v_x of A, B; 4, 5 = v_y of A, B.  Before the first step the buffer
+// holds the initial state itself, (rho_s - rho_ref_s, u, u), and the first
+// step reads it in place: the initial populations are local equilibria, not
+// streamed ones.
+struct MomF32 { using S = float;  using C = float; };
+struct MomF64 { using S = double; using C = double; };
+
+// Deviation of the equilibrium population i of one species from w_i rho_ref:
+// w_i [drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)], rho = rho_ref + drho.
+template <int I, class C>
+__device__ __forceinline__ C eq_dev(C drho, C rho, C vx, C vy)
+{
+    constexpr double W = (I == 0) ? 4.0 / 9.0 : (I < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    const C cu = (C)CX[I] * vx + (C)CY[I] * vy;
+    const C usq = vx * vx + vy * vy;
+    return (C)W * (drho + rho * ((C)3 * cu + (C)4.5 * cu * cu - (C)1.5 * usq));
+}
+
+template <class C>
+__host__ __device__ constexpr size_t mom_dyn_lds(int bx, int ly)
+{
+    return sizeof(double) * (size_t)(bx / 64) * ly;
+}
+
+template <int BX, class P>
+__global__ void __launch_bounds__(BX)
+k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __restrict__ tiles, int ntot,
+           int src, int first)
+{
+    using S = typename P::S;
+    using C = typename P::C;
+    using C2 = typename V2<C>::T;
+    // Moment rows in flight: four rows of the pairs (drho, v_x, v_y) of A and B
+    // for columns x0-3 .. x0+BX+2; psi and rho pairs of the six rows around the
+    // collided one for columns x0-2 .. x0+BX+1.
+    __shared__ C2 mring[4][3][BX + 6];
+    __shared__ C2 ringP[6][BX + 4];
+    __shared__ C2 ringR[6][BX + 4];
+    extern __shared__ __align__(16) char dyn_lds[];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+
+    for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
+        const int L = tiles[w];
+        if (L < 0) continue;
+        const LatDesc& d = descs[L];
+        const int l = w - d.item_begin;
+        if (l >= d.nitems) continue;
+        int lin = l;
+        if ((d.nitems & 7) == 0) {
+            const int c = d.nitems >> 3;
+            lin = (l & 7) * c + (l >> 3);
+        }
+        const int nstrip = d.nstrip;
+        const int strip = lin % nstrip, seg = lin / nstrip;
+        const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
+        const long long plane = d.plane;
+        const int x0 = strip * BX;
+        const int y0 = seg * d.ly;
+        const int y1 = min(y0 + d.ly, ny);
+        const unsigned x = (unsigned)(x0 + tid);
+        const bool valid = x < (unsigned)nx;
+        const unsigned xc = x % (unsigned)nx;
+        auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
+
+        const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
+        C ks0[5], ks1[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            ks0[k] = coef<C>(d.ks[0][k], d.fks[0][k]);
+            ks1[k] = coef<C>(d.ks[1][k], d.fks[1][k]);
+        }
+        const C kx1 = coef<C>(d.kx[0], d.fkx[0]), kx2 = coef<C>(d.kx[1], d.fkx[1]);
+        const C u_top = coef<C>(d.u_top, d.fu_top), u_bot = coef<C>(d.u_bot, d.fu_bot);
+        const C rref0 = coef<C>(d.rref[0], d.frref[0]), rref1 = coef<C>(d.rref[1], d.frref[1]);
+        const C pref0 = coef<C>(d.psiref[0], d.fpsiref[0]), pref1 = coef<C>(d.psiref[1], d.fpsiref[1]);
+        const C e0 = coef<C>(d.epsi[0], d.fepsi[0]), e1 = coef<C>(d.epsi[1], d.fepsi[1]);
+
+        const int es = (int)sizeof(S);
+        const unsigned mbytes = (unsigned)(6 * plane * (long long)es);
+        const rsrc_t rin = make_rsrc(base + d.off_f[src], mbytes);
+        const rsrc_t rout = make_rsrc(base + d.off_f[src ^ 1], mbytes);
+        const int pbytes = (int)(plane * es), rbytes = pitch * es;
+        const unsigned vc = xc * es;
+        // lanes 0..5: the moment halo columns x0-3, x0-2, x0-1, x0+BX, x0+BX+1,
+        // x0+BX+2; lanes 0..3: the psi halo columns x0-2, x0-1, x0+BX, x0+BX+1
+        // (local column indices hm, hp)
+        const int hm = (tid < 3) ? tid - 3 : BX + tid - 3;
+        const unsigned vhm = (unsigned)wrap(x0 + hm) * es;
+        const int hp = (tid < 2) ? tid - 2 : BX + tid - 2;
+        double* __restrict__ stress = (double*)(base + d.off_stress);
+        double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
+        const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
+        double* profS = (double*)dyn_lds;                   // [BX/64][ly]
+        C mom_b = 0, mom_t = 0;
+
+        // One moment row in registers: the lane's column and, for lanes 0..5,
+        // its halo column.  Rows beyond a wall do not exist and are skipped.
+        struct MR { C v[6]; C h[6]; };
+        auto mrow_ok = [&](int r) { return !walls || (r >= 0 && r < ny); };
+        auto mload = [&](MR& m, int r) {
+            if (!mrow_ok(r)) return;
+            const int so = map_row<P>(r, ny, walls) * rbytes;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) m.v[p] = ld<P>(rin, vc, so + p * pbytes);
+            if (tid < 6) {
+#pragma unroll
+                for (int p = 0; p < 6; ++p) m.h[p] = ld<P>(rin, vhm, so + p * pbytes);
+            }
+        };
+        auto mput = [&](const MR& m, int r) {
+            if (!mrow_ok(r)) return;
+            const int sl = r & 3;
+            mring[sl][0][tid + 3] = C2{m.v[0], m.v[1]};
+            mring[sl][1][tid + 3] = C2{m.v[2], m.v[3]};
+            mring[sl][2][tid + 3] = C2{m.v[4], m.v[5]};
+            if (tid < 6) {
+                mring[sl][0][hm + 3] = C2{m.h[0], m.h[1]};
+                mring[sl][1][hm + 3] = C2{m.h[2], m.h[3]};
+                mring[sl][2][hm + 3] = C2{m.h[4], m.h[5]};
+            }
+        };
+
+        // Incoming populations of row r (a fluid row) at local column xl, summed
+        // into the density deviations of A and B and the momentum j.
+        auto pull = [&](int r, int xl, C& dA, C& dB, C& jx, C& jy) {
+            if (first) {
+                const int sl = r & 3;
+                const C2 m0 = mring[sl][0][xl + 3], m1 = mring[sl][1][xl + 3], m2 = mring[sl][2][xl + 3];
+                dA = m0.x;
+                dB = m0.y;
+                const C ra = rref0 + dA, rb = rref1 + dB;
+                jx = ra * m1.x + rb * m1.y;
+                jy = ra * m2.x + rb * m2.y;
+                return;
+            }
+            const bool bot = walls && r == 0, top = walls && r == ny - 1;
+            dA = dB = jx = jy = 0;
+            auto one = [&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cx = CX[i], cy = CY[i];
+                C fa, fb;
+                if ((cy > 0 && bot) || (cy < 0 && top)) {
+                    // source beyond the wall: the site's own population OPP[i],
+                    // returned with the moving-wall term (1/6) rho_s c_ix u_w
+                    constexpr int o = OPP[i];
+                    const int sl = r & 3;
+                    const C2 m0 = mring[sl][0][xl + 3], m1 = mring[sl][1][xl + 3], m2 = mring[sl][2][xl + 3];
+                    const C ra = rref0 + m0.x, rb = rref1 + m0.y;
+                    const C uw = (cy > 0) ? u_bot : u_top;
+                    fa = eq_dev<o>(m0.x, ra, m1.x, m2.x);
+                    fb = eq_dev<o>(m0.y, rb, m1.y, m2.y);
+                    if (cx != 0) {
+                        fa += (C)(1.0 / 6.0) * ra * (C)cx * uw;
+                        fb += (C)(1.0 / 6.0) * rb * (C)cx * uw;
+                    }
+                } else {
+                    const int sl = (r - cy) & 3;
+                    const int cs = xl - cx + 3;
+                    const C2 m0 = mring[sl][0][cs], m1 = mring[sl][1][cs], m2 = mring[sl][2][cs];
+                    fa = eq_dev<i>(m0.x, rref0 + m0.x, m1.x, m2.x);
+                    fb = eq_dev<i>(m0.y, rref1 + m0.y, m1.y, m2.y);
+                }
+                dA += fa;
+                dB += fb;
+                if (cx != 0) jx += (C)cx * (fa + fb);
+                if (cy != 0) jy += (C)cy * (fa + fb);
+            };
+            one(std::integral_constant<int, 0>{});
+            one(std::integral_constant<int, 1>{});
+            one(std::integral_constant<int, 2>{});
+            one(std::integral_constant<int, 3>{});
+            one(std::integral_constant<int, 4>{});
+            one(std::integral_constant<int, 5>{});
+            one(std::integral_constant<int, 6>{});
+            one(std::integral_constant<int, 7>{});
+            one(std::integral_constant<int, 8>{});
+        };
+
+        auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 2) % 6); };
+        // Stage row r: (psi, rho) deviations of its columns into the rings (the
+        // lane's column, lanes 0..3 also a halo column) and the lane's momentum
+        // into J.  A row beyond a wall is the even mirror of the fluid rows.
+        auto stage = [&](int r, C2& J) {
+            const int sl = slot6(r);
+            if (walls && (r < 0 || r >= ny)) {
+                const int sm = slot6((r < 0) ? -1 - r : 2 * ny - 1 - r);
+                ringP[sl][tid + 2] = ringP[sm][tid + 2];
+                ringR[sl][tid + 2] = ringR[sm][tid + 2];
+                if (tid < 4) {
+                    ringP[sl][hp + 2] = ringP[sm][hp + 2];
+                    ringR[sl][hp + 2] = ringR[sm][hp + 2];
+                }
+                return;
+            }
+            C dA, dB, jx, jy;
+            pull(r, tid, dA, dB, jx, jy);
+            ringP[sl][tid + 2] = C2{dpsi_of(dA, e0, inv_rho0), dpsi_of(dB, e1, inv_rho0)};
+            ringR[sl][tid + 2] = C2{dA, dB};
+            J = C2{jx, jy};
+            if (tid < 4) {
+                C hA, hB, hx, hy;
+                pull(r, hp, hA, hB, hx, hy);
+                ringP[sl][hp + 2] = C2{dpsi_of(hA, e0, inv_rho0), dpsi_of(hB, e1, inv_rho0)};
+                ringR[sl][hp + 2] = C2{hA, hB};
+            }
+        };
+
+        // Collide row y: the force from the 5x5 neighbourhood, the shifted
+        // velocities (tau = 1) and the six new moments of the site.
+        auto collide = [&](int y, const C2& J) {
+            int sl[5];
+            sl[0] = __builtin_amdgcn_readfirstlane((y - y0) % 6);
+#pragma unroll
+            for (int k = 1; k < 5; ++k) sl[k] = (sl[k - 1] == 5) ? 0 : sl[k - 1] + 1;
+            C sxA = 0, syA = 0, sxB = 0, syB = 0, cxA = 0, cyA = 0, cxB = 0, cyB = 0;
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const C2 n = ringP[sl[dy + 2]][tid + 2 + dx];
+                    const int sh = shell_of(dx, dy);
+                    if (dx != 0) {
+                        sxA += (ks0[sh] * (C)dx) * n.x;
+                        sxB += (ks1[sh] * (C)dx) * n.y;
+                    }
+                    if (dy != 0) {
+                        syA += (ks0[sh] * (C)dy) * n.x;
+                        syB += (ks1[sh] * (C)dy) * n.y;
+                    }
+                    if (sh <= 1) {
+                        const C2 m = ringR[sl[dy + 2]][tid + 2 + dx];
+                        const C kk = (sh == 0) ? kx1 : kx2;
+                        if (dx != 0) { cxA += (kk * (C)dx) * m.y; cxB += (kk * (C)dx) * m.x; }
+                        if (dy != 0) { cyA += (kk * (C)dy) * m.y; cyB += (kk * (C)dy) * m.x; }
+                    }
+                }
+                asm volatile("" : "+v"(sxA), "+v"(syA), "+v"(sxB), "+v"(syB), "+v"(cxA), "+v"(cyA),
+                             "+v"(cxB), "+v"(cyB)::"memory");
+            }
+            const C2 p0 = ringP[sl[2]][tid + 2];
+            const C2 r0c = ringR[sl[2]][tid + 2];
+            const C ra = rref0 + r0c.x, rb = rref1 + r0c.y;
+            const C pa = pref0 + p0.x, pb = pref1 + p0.y;
+            const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
+            const C FxB = -pb * sxB - rb * cxB, FyB = -pb * syB - rb * cyB;
+            const C inv_rho = rcp(ra + rb);
+            const C ux = J.x * inv_rho, uy = J.y * inv_rho;
+            const C gx = (body != nullptr) ? (C)body[y] * inv_rho : (C)0;
+            if (prof != nullptr && x0 + 64 * wave < nx) {
+                double su = valid ? (double)ux : 0.0;
+                su = wave_sum(su);
+                if ((tid & 63) == 0) profS[wave * d.ly + (y - y0)] = su;
+            }
+            const C iA = rcp(ra), iB = rcp(rb);
+            const C vAx = ux + (FxA * iA + gx), vAy = uy + FyA * iA;
+            const C vBx = ux + (FxB * iB + gx), vBy = uy + FyB * iB;
+            if (!valid) return;
+            const int so = y * rbytes;
+            st<P>(rout, vc, so, r0c.x);
+            st<P>(rout, vc, so + pbytes, r0c.y);
+            st<P>(rout, vc, so + 2 * pbytes, vAx);
+            st<P>(rout, vc, so + 3 * pbytes, vBx);
+            st<P>(rout, vc, so + 4 * pbytes, vAy);
+            st<P>(rout, vc, so + 5 * pbytes, vBy);
+            // wall momentum of the links that leave through a wall this step:
+            // c_ix (f*_i + back), back = f*_i - (1/6) rho_s c_ix u_w
+            if (walls && (y == 0 || y == ny - 1)) {
+                auto link = [&](auto I, C uw, C& acc) {
+                    constexpr int i = decltype(I)::value;
+                    constexpr int cx = CX[i];
+                    const C fa = (C)(i < 5 ? 1.0 / 9.0 : 1.0 / 36.0) * ra + eq_dev<i>((C)0, ra, vAx, vAy);
+                    const C fb = (C)(i < 5 ? 1.0 / 9.0 : 1.0 / 36.0) * rb + eq_dev<i>((C)0, rb, vBx, vBy);
+                    const C ba = fa - (C)(1.0 / 6.0) * ra * (C)cx * uw;
+                    const C bb = fb - (C)(1.0 / 6.0) * rb * (C)cx * uw;
+                    acc += (C)cx * (fa + ba) + (C)cx * (fb + bb);
+                };
+                if (y == 0) {
+                    link(std::integral_constant<int, 7>{}, u_bot, mom_b);
+                    link(std::integral_constant<int, 8>{}, u_bot, mom_b);
+                }
+                if (y == ny - 1) {
+                    link(std::integral_constant<int, 5>{}, u_top, mom_t);
+                    link(std::integral_constant<int, 6>{}, u_top, mom_t);
+                }
+            }
+        };
+
+        // Prologue: moment rows y0-3 .. y0+3 through the ring, psi/rho rows
+        // y0-2 .. y0+1 staged (fluid rows first, then the mirrored ghost rows),
+        // row y0+4 prefetched.  Loop: entering iteration y, moment rows
+        // y+1 .. y+3 are in LDS, row y+4 in registers, and psi/rho rows
+        // y-2 .. y+1 staged.
+        C2 J0 = C2{0, 0}, J1 = C2{0, 0}, J2 = C2{0, 0}, J3 = C2{0, 0}, Jx = C2{0, 0};
+        {
+            MR a, b, c, e;
+            mload(a, y0 - 3);
+            mload(b, y0 - 2);
+            mload(c, y0 - 1);
+            mload(e, y0);
+            mput(a, y0 - 3);
+            mput(b, y0 - 2);
+            mput(c, y0 - 1);
+            mput(e, y0);
+            lds_barrier();
+            if (mrow_ok(y0 - 2)) stage(y0 - 2, Jx);
+            if (mrow_ok(y0 - 1)) stage(y0 - 1, Jx);
+            lds_barrier();
+            mload(a, y0 + 1);
+            mload(b, y0 + 2);
+            mput(a, y0 + 1);
+            mput(b, y0 + 2);
+            lds_barrier();
+            if (mrow_ok(y0)) stage(y0, J0);
+            if (mrow_ok(y0 + 1)) stage(y0 + 1, J1);
+            for (int r = y0 - 2; r <= y0 + 1; ++r)
+                if (!mrow_ok(r)) stage(r, Jx);
+            lds_barrier();
+            mload(a, y0 + 3);
+            mput(a, y0 + 3);
+        }
+        MR pf;
+        if (y0 + 4 <= y1 + 2) mload(pf, y0 + 4);
+        lds_barrier();
+        auto iter = [&](int y, const C2& Jc, C2& Js) {
+            if (y + 4 <= y1 + 2) mput(pf, y + 4);
+            if (y + 5 <= y1 + 2) mload(pf, y + 5);
+            stage(y + 2, Js);
+            lds_barrier();
+            collide(y, Jc);
+        };
+        for (int y = y0; y < y1; y += 4) {
+            iter(y, J0, J2);
+            if (y + 1 < y1) iter(y + 1, J1, J3);
+            if (y + 2 < y1) iter(y + 2, J2, J0);
+            if (y + 3 < y1) iter(y + 3, J3, J1);
+        }
+        if (valid && walls && y0 == 0) stress[xc] += (double)mom_b;
+        if (valid && walls && y1 == ny) stress[nx + xc] += (double)mom_t;
+        __syncthreads();
+        if (prof != nullptr) {
+            const int nr = y1 - y0;
+            for (int e = tid; e < (BX / 64) * nr; e += BX) {
+                const int wv = e / nr, r = e % nr;
+                if (x0 + 64 * wv < nx) prof[(long long)(x0 / 64 + wv) * ny + y0 + r] += profS[wv * d.ly + r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Population i of species s at site (x, y) in the moment form, FP64: the
+// equilibrium of its source site, across a wall the bounced population of the
+// site itself, or, before the first step, the local equilibrium.
+template <class P>
+__device__ double mom_pop(const LatDesc& d, const typename P::S* m, int first, int x, int y, int s, int i)
+{
+    int xs = x, ys = y, q = i;
+    double extra = 0;
+    if (!first) {
+        const int cx = CX[i], cy = CY[i];
+        if (d.walls && ((cy > 0 && y == 0) || (cy < 0 && y == d.ny - 1))) {
+            q = OPP[i];
+            const double uw = (cy > 0) ? d.u_bot : d.u_top;
+            extra = (1.0 / 6.0) * (d.rref[s] + (double)m[s * d.plane + (long long)y * d.pitch + x]) * cx * uw;
+        } else {
+            xs = x - cx;
+            xs = xs < 0 ? xs + d.nx : (xs >= d.nx ? xs - d.nx : xs);
+            ys = y - cy;
+            ys = ys < 0 ? ys + d.ny : (ys >= d.ny ? ys - d.ny : ys);
+        }
+    }
+    const long long o = (long long)ys * d.pitch + xs;
+    const double rho = d.rref[s] + (double)m[s * d.plane + o];
+    const double vx = (double)m[(2 + s) * d.plane + o], vy = (double)m[(4 + s) * d.plane + o];
+    const double w = (q == 0) ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    const double cu = CX[q] * vx + CY[q] * vy;
+    return w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (vx * vx + vy * vy)) + extra;
+}
+
+// Initial state of the moment form: (rho_s - rho_ref_s, u, u).
+template <class P>
+__global__ void k_init_mom(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf,
+                           const double* __restrict__ ra, const double* __restrict__ rb,
+                           const double* __restrict__ ux, const double* __restrict__ uy)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    S* m = (S*)(base + d.off_f[buf]);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        const long long o = (long long)y * d.pitch + x;
+        const double u = ux ? ux[k] : 0.0, v = uy ? uy[k] : 0.0;
+        m[o] = (S)(ra[k] - d.rref[0]);
+        m[d.plane + o] = (S)(rb[k] - d.rref[1]);
+        m[2 * d.plane + o] = (S)u;
+        m[3 * d.plane + o] = (S)u;
+        m[4 * d.plane + o] = (S)v;
+        m[5 * d.plane + o] = (S)v;
+    }
+}
+
+template <class P>
+__global__ void k_fields_mom(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, int first,
+                             double* __restrict__ ra, double* __restrict__ rb,
+                             double* __restrict__ ux, double* __restrict__ uy)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const S* m = (const S*)(base + d.off_f[buf]);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        double rho[2] = {0, 0}, jx = 0, jy = 0;
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 9; ++i) {
+                const double v = mom_pop<P>(d, m, first, x, y, s, i);
+                rho[s] += v;
+                jx += v * CX[i];
+                jy += v * CY[i];
+            }
+        if (ra) ra[k] = rho[0];
+        if (rb) rb[k] = rho[1];
+        if (ux) ux[k] = jx / (rho[0] + rho[1]);
+        if (uy) uy[k] = jy / (rho[0] + rho[1]);
+    }
+}
+
+template <class P>
+__global__ void k_export_mom(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, int first, int q,
+                             double* __restrict__ out)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const S* m = (const S*)(base + d.off_f[buf]);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        out[k] = mom_pop<P>(d, m, first, x, y, q / 9, q % 9);
+    }
+}
+
+template <class P>
+__global__ void __launch_bounds__(RED_THREADS)
+k_sums_mom(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, int first,
+           double* __restrict__ partials)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const long long n = (long long)d.nx * d.ny;
+    const S* m = (const S*)(base + d.off_f[buf]);
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k % d.nx);
+        double rho[2] = {0, 0};
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 9; ++i) {
+                const double v = mom_pop<P>(d, m, first, x, y, s, i);
+                rho[s] += v;
+                acc[2] += v * CX[i];
+                acc[3] += v * CY[i];
+            }
+        acc[0] += rho[0];
+        acc[1] += rho[1];
+        const bool ok = (rho[0] > 0.0) && (rho[1] > 0.0) && (rho[0] < 1e300) && (rho[1] < 1e300);
+        if (!ok) acc[4] += 1.0;
+    }
+    __shared__ double red[RED_THREADS / 64][5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[q] = wave_sum(acc[q]);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 5; ++q) red[wave][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double t = 0;
+        for (int wv = 0; wv < RED_THREADS / 64; ++wv) t += red[wv][threadIdx.x];
+        partials[blockIdx.x * 5 + threadIdx.x] = t;
+    }
+}
+
+template <class P>
+__global__ void __launch_bounds__(256)
+k_line_profile_mom(char* __restrict__ base, const LatDesc* __restrict__ dd, int buf, int first,
+                   double* __restrict__ out)
+{
+    using S = typename P::S;
+    const LatDesc& d = *dd;
+    const int y = blockIdx.x;
+    const S* m = (const S*)(base + d.off_f[buf]);
+    double acc = 0;
+    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
+        double rho = 0, jx = 0;
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 9; ++i) {
+                const double v = mom_pop<P>(d, m, first, x, y, s, i);
+                rho += v;
+                jx += v * CX[i];
+            }
+        acc += jx / rho;
+    }
+    __shared__ double red[4];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[y] = (red[0] + red[1] + red[2] + red[3]) / d.nx;
+}
+
 // ---------------------------------------------------------- host launchers --
 
 template <int BX, class P>
@@ -868,9 +1396,39 @@ static hipError_t step_p(int bx, char* base, const LatDesc* descs, const int* ti
     default: return hipErrorInvalidValue;                            \
     }
 
-hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
-                       int src, int grid, int ly, hipStream_t s)
+template <int BX, class P>
+static hipError_t step_mom_bx(char* base, const LatDesc* descs, const int* tiles, int ntot, int src, int first,
+                              int grid, int ly, hipStream_t s)
 {
+    const size_t dyn = mom_dyn_lds<typename P::C>(BX, ly);
+    hipLaunchKernelGGL((k_step_mom<BX, P>), dim3(grid), dim3(BX), dyn, s, base, descs, tiles, ntot, src, first);
+    return hipGetLastError();
+}
+
+template <class P>
+static hipError_t step_mom_p(int bx, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
+                             int first, int grid, int ly, hipStream_t s)
+{
+    switch (bx) {
+    case 64: return step_mom_bx<64, P>(base, descs, tiles, ntot, src, first, grid, ly, s);
+    case 128: return step_mom_bx<128, P>(base, descs, tiles, ntot, src, first, grid, ly, s);
+    case 256: return step_mom_bx<256, P>(base, descs, tiles, ntot, src, first, grid, ly, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Moment-form storage (tau = 1): codes 4 (FP32) and 5 (FP64).
+#define LBK_DISPATCH_MOM(storage, CALL)                              \
+    switch (storage) {                                               \
+    case 4: { using P = MomF32; return CALL; }                       \
+    case 5: { using P = MomF64; return CALL; }                       \
+    default: break;                                                  \
+    }
+
+hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
+                       int src, int first, int grid, int ly, hipStream_t s)
+{
+    LBK_DISPATCH_MOM(storage, (step_mom_p<P>(bx, base, descs, tiles, ntot, src, first, grid, ly, s)));
     LBK_DISPATCH(storage, (step_p<P>(bx, base, descs, tiles, ntot, src, grid, ly, s)));
 }
 
@@ -890,10 +1448,19 @@ static hipError_t init_p(char* base, const LatDesc* d, long long n, int buf, con
     return hipGetLastError();
 }
 
+template <class P>
+static hipError_t init_mom_p(char* base, const LatDesc* d, long long n, int buf, const double* ra,
+                             const double* rb, const double* ux, const double* uy, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init_mom<P>), dim3(grid_for(n, 256)), dim3(256), 0, s, base, d, buf, ra, rb, ux, uy);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(int storage, char* base, const LatDesc* d, long long nsites, int buf,
                        const double* ra, const double* rb, const double* ux, const double* uy,
                        hipStream_t s)
 {
+    LBK_DISPATCH_MOM(storage, (init_mom_p<P>(base, d, nsites, buf, ra, rb, ux, uy, s)));
     LBK_DISPATCH(storage, (init_p<P>(base, d, nsites, buf, ra, rb, ux, uy, s)));
 }
 
@@ -905,9 +1472,19 @@ static hipError_t fields_p(char* base, const LatDesc* d, long long n, int buf, d
     return hipGetLastError();
 }
 
-hipError_t launch_fields(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+template <class P>
+static hipError_t fields_mom_p(char* base, const LatDesc* d, long long n, int buf, int first, double* ra,
+                               double* rb, double* ux, double* uy, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fields_mom<P>), dim3(grid_for(n, 256)), dim3(256), 0, s, base, d, buf, first, ra, rb, ux,
+                       uy);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int storage, char* base, const LatDesc* d, long long nsites, int buf, int first,
                          double* ra, double* rb, double* ux, double* uy, hipStream_t s)
 {
+    LBK_DISPATCH_MOM(storage, (fields_mom_p<P>(base, d, nsites, buf, first, ra, rb, ux, uy, s)));
     LBK_DISPATCH(storage, (fields_p<P>(base, d, nsites, buf, ra, rb, ux, uy, s)));
 }
 
@@ -919,9 +1496,18 @@ static hipError_t export_p(char* base, const LatDesc* d, long long n, int buf, i
     return hipGetLastError();
 }
 
-hipError_t launch_export(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+template <class P>
+static hipError_t export_mom_p(char* base, const LatDesc* d, long long n, int buf, int first, int q, double* out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL((k_export_mom<P>), dim3(grid_for(n, 256)), dim3(256), 0, s, base, d, buf, first, q, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(int storage, char* base, const LatDesc* d, long long nsites, int buf, int first,
                          int q, double* out, hipStream_t s)
 {
+    LBK_DISPATCH_MOM(storage, (export_mom_p<P>(base, d, nsites, buf, first, q, out, s)));
     LBK_DISPATCH(storage, (export_p<P>(base, d, nsites, buf, q, out, s)));
 }
 
@@ -934,9 +1520,19 @@ static hipError_t sums_p(char* base, const LatDesc* d, int buf, int nblocks, dou
     return hipGetLastError();
 }
 
-hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int nblocks,
+template <class P>
+static hipError_t sums_mom_p(char* base, const LatDesc* d, int buf, int first, int nblocks, double* partials,
+                             double* out, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sums_mom<P>), dim3(nblocks), dim3(RED_THREADS), 0, s, base, d, buf, first, partials);
+    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, s, partials, nblocks, out, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int first, int nblocks,
                        double* partials, double* out, int* flag, hipStream_t s)
 {
+    LBK_DISPATCH_MOM(storage, (sums_mom_p<P>(base, d, buf, first, nblocks, partials, out, flag, s)));
     LBK_DISPATCH(storage, (sums_p<P>(base, d, buf, nblocks, partials, out, flag, s)));
 }
 
@@ -947,9 +1543,18 @@ static hipError_t line_profile_p(char* base, const LatDesc* desc, int ny, int bu
     return hipGetLastError();
 }
 
-hipError_t launch_line_profile(int storage, char* base, const LatDesc* desc, int ny, int buf, double* out,
-                               hipStream_t s)
+template <class P>
+static hipError_t line_profile_mom_p(char* base, const LatDesc* desc, int ny, int buf, int first, double* out,
+                                     hipStream_t s)
 {
+    hipLaunchKernelGGL(k_line_profile_mom<P>, dim3(ny), dim3(256), 0, s, base, desc, buf, first, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_profile(int storage, char* base, const LatDesc* desc, int ny, int buf, int first,
+                               double* out, hipStream_t s)
+{
+    LBK_DISPATCH_MOM(storage, (line_profile_mom_p<P>(base, desc, ny, buf, first, out, s)));
     LBK_DISPATCH(storage, (line_profile_p<P>(base, desc, ny, buf, out, s)));
 }
 

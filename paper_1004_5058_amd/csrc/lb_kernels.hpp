@@ -8,19 +8,21 @@
 namespace lbk {
 
 // ly: the largest rows-per-tile of the lattices (sizes the dynamic LDS).
+// first: the step starts from the initial state (moment storage only: it then
+// reads the local equilibria in place instead of pulling from neighbours).
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
-                       int src, int grid, int ly, hipStream_t s);
+                       int src, int first, int grid, int ly, hipStream_t s);
 hipError_t launch_init(int storage, char* base, const LatDesc* d, long long nsites, int buf,
                        const double* ra, const double* rb, const double* ux, const double* uy,
                        hipStream_t s);
-hipError_t launch_fields(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+hipError_t launch_fields(int storage, char* base, const LatDesc* d, long long nsites, int buf, int first,
                          double* ra, double* rb, double* ux, double* uy, hipStream_t s);
-hipError_t launch_export(int storage, char* base, const LatDesc* d, long long nsites, int buf,
+hipError_t launch_export(int storage, char* base, const LatDesc* d, long long nsites, int buf, int first,
                          int q, double* out, hipStream_t s);
-hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int nblocks,
+hipError_t launch_sums(int storage, char* base, const LatDesc* d, int buf, int first, int nblocks,
                        double* partials, double* out, int* flag, hipStream_t s);
-hipError_t launch_line_profile(int storage, char* base, const LatDesc* desc, int ny, int buf, double* out,
-                               hipStream_t s);
+hipError_t launch_line_profile(int storage, char* base, const LatDesc* desc, int ny, int buf, int first,
+                               double* out, hipStream_t s);
 hipError_t launch_stress_reduce(char* base, const LatDesc* descs, int nlat, double* out, hipStream_t s);
 hipError_t launch_profile_reduce(char* base, const LatDesc* d, int ny, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "liblbmi.so")
 
-STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
+STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3, "mom32": 4, "mom64": 5}
 STATUS = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", -4: "LB_ENONFINITE",
           -5: "LB_ESTATE"}
 

@@ -106,3 +106,29 @@ def test_init_rejects_bad_inputs_before_device_work():
                      ctypes.byref(h)) == -2
     assert b"smaller" in L.lb_last_error()
     assert L.lb_step(None, 1) == -1
+
+
+def test_moment_storage_requires_tau_one():
+    """The moment form holds the post-collision state only at tau = 1."""
+    from paper_1004_5058_amd import lb
+    lb.load_library()
+    with pytest.raises(lb.LBError, match="tau = 1"):
+        lb.lb_state_bytes(lb.make_params(32, 16, tau=0.8, storage="mom32"))
+    assert lb.lb_state_bytes(lb.make_params(32, 16, tau=1.0, storage="mom32")) > 0
+    # 6 moments per site instead of 18 populations (each buffer padded to the
+    # 32 bytes per site of the FP64 staging: 2 x 32 instead of 2 x 72)
+    m = lb.lb_state_bytes(lb.make_params(256, 256, tau=1.0, storage="mom32"))
+    f = lb.lb_state_bytes(lb.make_params(256, 256, tau=1.0, storage="f32"))
+    assert m < 0.5 * f
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev", "mom32", "mom64"])
+@pytest.mark.parametrize("nx,ny", [(64, 48), (128, 20), (131, 37)])
+def test_state_buffers_hold_the_fp64_staging(storage, nx, ny):
+    """Initial fields and field reads are staged as four FP64 arrays in a state
+    buffer, so each of the two buffers holds at least 32 bytes per site (the
+    FP32 moment form stores only 24)."""
+    from paper_1004_5058_amd import lb
+    lb.load_library()
+    n = lb.lb_state_bytes(lb.make_params(nx, ny, tau=1.0, storage=storage))
+    assert n >= 2 * 32 * nx * ny
