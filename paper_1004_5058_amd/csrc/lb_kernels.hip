@@ -1017,6 +1017,9 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
                 dB += fb;
                 if (cx != 0) jx += (C)cx * (fa + fb);
                 if (cy != 0) jy += (C)cy * (fa + fb);
+                // keep each direction's LDS reads next to their arithmetic (bounds
+                // the registers the pull occupies: three waves per SIMD)
+                asm volatile("" : "+v"(dA), "+v"(dB), "+v"(jx), "+v"(jy)::"memory");
             };
             one(std::integral_constant<int, 0>{});
             one(std::integral_constant<int, 1>{});
