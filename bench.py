@@ -6,7 +6,11 @@ linear Couette velocity, symmetric couplings G^a = -9.0, G^r = 8.1 (both
 species), G_AB = 0.405, rho0 = 0.83, tau = 1.  A step is one full time step of
 both species: pseudo-potential, belt-1/two-belt forces, BGK collision,
 streaming, walls and the FP64 wall-stress accumulation.  Populations are FP32
-(headline `value`); FP16- and BF16-deviation storage are timed beside it.
+(headline `value`); FP16- and BF16-deviation storage are timed beside it, and
+so is the moment form ("mom32": at tau = 1 the post-collision state is six
+moments per site, 48 bytes per update instead of 144).  Each variant's
+`frac` is against its own byte floor; the roofline object is the FP32
+population step's.
 
 Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
 step (18 population loads + 18 stores per site) divided by the step kernel's
@@ -18,7 +22,7 @@ flow-curve points per hour on the batched 48-lattice ensemble (10 000 steps
 each) against a plain one-lattice-at-a-time loop.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--variants f32,f16dev,bf16dev] [--size 4096] [--no-flowcurve] [--no-tune]
+       [--variants f32,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve] [--no-tune]
 """
 import argparse
 import hashlib
@@ -31,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72, "bf16dev": 72}
+BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72, "bf16dev": 72, "mom32": 48, "mom64": 96}
 
 
 def kernel_source_hash():
@@ -139,7 +143,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--variants", default="f32,f16dev,bf16dev")
+    ap.add_argument("--variants", default="f32,f16dev,bf16dev,mom32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flowcurve", action="store_true", help="skip the batched-vs-plain flow-curve leg")
     ap.add_argument("--flow-steps", type=int, default=10000)
@@ -199,7 +203,8 @@ def main():
         "variants": {v: {"mlups": round(res[v]["mlups"], 1), "ms_kernel": round(res[v]["ms_kernel"], 5),
                          "launch_shape": res[v]["shape"],
                          "alg_gbs": round(BYTES_PER_LUP[v] * float(n) * n / (res[v]["ms_kernel"] * 1e-3) / 1e9, 1),
-                         "bytes_per_lup": BYTES_PER_LUP[v]} for v in variants},
+                         "bytes_per_lup": BYTES_PER_LUP[v],
+                         "sigma_bot_top": [float(f"{x:.7e}") for x in res[v]["stress"]]} for v in variants},
     }
     for v in variants:
         line["variants"][v]["frac"] = round(line["variants"][v]["alg_gbs"] / HBM_PEAK_GBS, 4)
