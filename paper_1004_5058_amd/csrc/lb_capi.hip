@@ -129,7 +129,9 @@ Layout plan(std::vector<Lat>& lats)
         const size_t es = storage_size(a.p.storage);
         a.pitch = (int)align_up((size_t)a.p.nx, 64);
         a.plane = (long long)a.pitch * a.p.ny;
-        a.ngroups = (a.p.nx + 63) / 64;
+        // profile accumulator rows: one per 64 columns, or for the moment form
+        // one per tile of the narrowest launch shape (60 collided columns)
+        a.ngroups = is_mom(a.p.storage) ? (a.p.nx + 59) / 60 : (a.p.nx + 63) / 64;
         // Each state buffer also serves as staging for four FP64 arrays of
         // nx*ny values (initial fields, field reads): at least 32 bytes per
         // site, whatever the storage needs (6 FP32 moments need only 24).
@@ -258,7 +260,9 @@ lb_status decompose(lbb_handle* h)
     for (size_t k = 0; k < h->lats.size(); ++k) {
         const Lat& a = h->lats[k];
         lbk::LatDesc& d = h->descs[k];
-        d.nstrip = (a.p.nx + h->bx - 1) / h->bx;
+        // the moment form's tiles overlap by four columns: bx - 4 collided per tile
+        const int wt = is_mom(h->storage) ? h->bx - 4 : h->bx;
+        d.nstrip = (a.p.nx + wt - 1) / wt;
         d.ly = std::min(std::min(h->ly, a.p.ny), 256);   // the kernel's halo buffer holds 256 rows
         d.nseg = (a.p.ny + d.ly - 1) / d.ly;
         h->ly_max = std::max(h->ly_max, d.ly);

@@ -881,12 +881,15 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
     using S = typename P::S;
     using C = typename P::C;
     using C2 = typename V2<C>::T;
+    // Overlapped tiles: the BX lanes hold columns x0-2 .. x0+BX-3 and every
+    // lane rebuilds its own column, so the psi/rho neighbourhood of the BX-4
+    // columns x0 .. x0+BX-5 that the tile collides needs no extra halo work.
     // Moment rows in flight: four rows of the pairs (drho, v_x, v_y) of A and B
-    // for columns x0-3 .. x0+BX+2; psi and rho pairs of the six rows around the
-    // collided one for columns x0-2 .. x0+BX+1.
-    __shared__ C2 mring[4][3][BX + 6];
-    __shared__ C2 ringP[6][BX + 4];
-    __shared__ C2 ringR[6][BX + 4];
+    // for columns x0-3 .. x0+BX-2 (index column - x0 + 3); psi and rho pairs of
+    // the six rows around the collided one for the lanes' columns (index tid).
+    __shared__ C2 mring[4][3][BX + 2];
+    __shared__ C2 ringP[6][BX];
+    __shared__ C2 ringR[6][BX];
     extern __shared__ __align__(16) char dyn_lds[];
 
     const int tid = threadIdx.x;
@@ -907,13 +910,13 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         const int strip = lin % nstrip, seg = lin / nstrip;
         const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
         const long long plane = d.plane;
-        const int x0 = strip * BX;
+        const int x0 = strip * (BX - 4);
         const int y0 = seg * d.ly;
         const int y1 = min(y0 + d.ly, ny);
-        const unsigned x = (unsigned)(x0 + tid);
-        const bool valid = x < (unsigned)nx;
-        const unsigned xc = x % (unsigned)nx;
         auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
+        const int x = x0 - 2 + tid;                       // the lane's column
+        const bool valid = tid >= 2 && tid < BX - 2 && x < nx;   // collided by this tile
+        const unsigned xc = (unsigned)wrap(x);
 
         const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
         C ks0[5], ks1[5];
@@ -934,20 +937,19 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         const rsrc_t rout = make_rsrc(base + d.off_f[src ^ 1], mbytes);
         const int pbytes = (int)(plane * es), rbytes = pitch * es;
         const unsigned vc = xc * es;
-        // lanes 0..5: the moment halo columns x0-3, x0-2, x0-1, x0+BX, x0+BX+1,
-        // x0+BX+2; lanes 0..3: the psi halo columns x0-2, x0-1, x0+BX, x0+BX+1
-        // (local column indices hm, hp)
-        const int hm = (tid < 3) ? tid - 3 : BX + tid - 3;
-        const unsigned vhm = (unsigned)wrap(x0 + hm) * es;
-        const int hp = (tid < 2) ? tid - 2 : BX + tid - 2;
+        const int cm = tid + 1;                           // the lane's moment-ring index
+        // lanes 0 and 1 also load the two outer moment columns x0-3 and
+        // x0+BX-2 (ring indices 0 and BX+1)
+        const int hm = (tid == 0) ? 0 : BX + 1;
+        const unsigned vhm = (unsigned)wrap(x0 - 3 + hm) * es;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
-        double* profS = (double*)dyn_lds;                   // [BX/64][ly]
+        double* profS = (double*)dyn_lds;                   // [BX/64][ly] per-wave row sums
         C mom_b = 0, mom_t = 0;
 
-        // One moment row in registers: the lane's column and, for lanes 0..5,
-        // its halo column.  Rows beyond a wall do not exist and are skipped.
+        // One moment row in registers: the lane's column and, for lanes 0 and
+        // 1, an outer column.  Rows beyond a wall do not exist and are skipped.
         struct MR { C v[6]; C h[6]; };
         auto mrow_ok = [&](int r) { return !walls || (r >= 0 && r < ny); };
         auto mload = [&](MR& m, int r) {
@@ -955,7 +957,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
             const int so = map_row<P>(r, ny, walls) * rbytes;
 #pragma unroll
             for (int p = 0; p < 6; ++p) m.v[p] = ld<P>(rin, vc, so + p * pbytes);
-            if (tid < 6) {
+            if (tid < 2) {
 #pragma unroll
                 for (int p = 0; p < 6; ++p) m.h[p] = ld<P>(rin, vhm, so + p * pbytes);
             }
@@ -963,22 +965,22 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         auto mput = [&](const MR& m, int r) {
             if (!mrow_ok(r)) return;
             const int sl = r & 3;
-            mring[sl][0][tid + 3] = C2{m.v[0], m.v[1]};
-            mring[sl][1][tid + 3] = C2{m.v[2], m.v[3]};
-            mring[sl][2][tid + 3] = C2{m.v[4], m.v[5]};
-            if (tid < 6) {
-                mring[sl][0][hm + 3] = C2{m.h[0], m.h[1]};
-                mring[sl][1][hm + 3] = C2{m.h[2], m.h[3]};
-                mring[sl][2][hm + 3] = C2{m.h[4], m.h[5]};
+            mring[sl][0][cm] = C2{m.v[0], m.v[1]};
+            mring[sl][1][cm] = C2{m.v[2], m.v[3]};
+            mring[sl][2][cm] = C2{m.v[4], m.v[5]};
+            if (tid < 2) {
+                mring[sl][0][hm] = C2{m.h[0], m.h[1]};
+                mring[sl][1][hm] = C2{m.h[2], m.h[3]};
+                mring[sl][2][hm] = C2{m.h[4], m.h[5]};
             }
         };
 
-        // Incoming populations of row r (a fluid row) at local column xl, summed
-        // into the density deviations of A and B and the momentum j.
-        auto pull = [&](int r, int xl, C& dA, C& dB, C& jx, C& jy) {
+        // Incoming populations of row r (a fluid row) at the lane's column,
+        // summed into the density deviations of A and B and the momentum j.
+        auto pull = [&](int r, C& dA, C& dB, C& jx, C& jy) {
             if (first) {
                 const int sl = r & 3;
-                const C2 m0 = mring[sl][0][xl + 3], m1 = mring[sl][1][xl + 3], m2 = mring[sl][2][xl + 3];
+                const C2 m0 = mring[sl][0][cm], m1 = mring[sl][1][cm], m2 = mring[sl][2][cm];
                 dA = m0.x;
                 dB = m0.y;
                 const C ra = rref0 + dA, rb = rref1 + dB;
@@ -997,7 +999,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
                     // returned with the moving-wall term (1/6) rho_s c_ix u_w
                     constexpr int o = OPP[i];
                     const int sl = r & 3;
-                    const C2 m0 = mring[sl][0][xl + 3], m1 = mring[sl][1][xl + 3], m2 = mring[sl][2][xl + 3];
+                    const C2 m0 = mring[sl][0][cm], m1 = mring[sl][1][cm], m2 = mring[sl][2][cm];
                     const C ra = rref0 + m0.x, rb = rref1 + m0.y;
                     const C uw = (cy > 0) ? u_bot : u_top;
                     fa = eq_dev<o>(m0.x, ra, m1.x, m2.x);
@@ -1008,7 +1010,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
                     }
                 } else {
                     const int sl = (r - cy) & 3;
-                    const int cs = xl - cx + 3;
+                    const int cs = cm - cx;
                     const C2 m0 = mring[sl][0][cs], m1 = mring[sl][1][cs], m2 = mring[sl][2][cs];
                     fa = eq_dev<i>(m0.x, rref0 + m0.x, m1.x, m2.x);
                     fb = eq_dev<i>(m0.y, rref1 + m0.y, m1.y, m2.y);
@@ -1033,32 +1035,22 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         };
 
         auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 2) % 6); };
-        // Stage row r: (psi, rho) deviations of its columns into the rings (the
-        // lane's column, lanes 0..3 also a halo column) and the lane's momentum
-        // into J.  A row beyond a wall is the even mirror of the fluid rows.
+        // Stage row r: (psi, rho) deviations of the lane's column into the
+        // rings and its momentum into J.  A row beyond a wall is the even
+        // mirror of the fluid rows.
         auto stage = [&](int r, C2& J) {
             const int sl = slot6(r);
             if (walls && (r < 0 || r >= ny)) {
                 const int sm = slot6((r < 0) ? -1 - r : 2 * ny - 1 - r);
-                ringP[sl][tid + 2] = ringP[sm][tid + 2];
-                ringR[sl][tid + 2] = ringR[sm][tid + 2];
-                if (tid < 4) {
-                    ringP[sl][hp + 2] = ringP[sm][hp + 2];
-                    ringR[sl][hp + 2] = ringR[sm][hp + 2];
-                }
+                ringP[sl][tid] = ringP[sm][tid];
+                ringR[sl][tid] = ringR[sm][tid];
                 return;
             }
             C dA, dB, jx, jy;
-            pull(r, tid, dA, dB, jx, jy);
-            ringP[sl][tid + 2] = C2{dpsi_of(dA, e0, inv_rho0), dpsi_of(dB, e1, inv_rho0)};
-            ringR[sl][tid + 2] = C2{dA, dB};
+            pull(r, dA, dB, jx, jy);
+            ringP[sl][tid] = C2{dpsi_of(dA, e0, inv_rho0), dpsi_of(dB, e1, inv_rho0)};
+            ringR[sl][tid] = C2{dA, dB};
             J = C2{jx, jy};
-            if (tid < 4) {
-                C hA, hB, hx, hy;
-                pull(r, hp, hA, hB, hx, hy);
-                ringP[sl][hp + 2] = C2{dpsi_of(hA, e0, inv_rho0), dpsi_of(hB, e1, inv_rho0)};
-                ringR[sl][hp + 2] = C2{hA, hB};
-            }
         };
 
         // Collide row y: the force from the 5x5 neighbourhood, the shifted
@@ -1074,7 +1066,8 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
 #pragma unroll
                 for (int dx = -2; dx <= 2; ++dx) {
                     if (dx == 0 && dy == 0) continue;
-                    const C2 n = ringP[sl[dy + 2]][tid + 2 + dx];
+                    const int cn = min(max(tid + dx, 0), BX - 1);   // edge lanes are not collided
+                    const C2 n = ringP[sl[dy + 2]][cn];
                     const int sh = shell_of(dx, dy);
                     if (dx != 0) {
                         sxA += (ks0[sh] * (C)dx) * n.x;
@@ -1085,7 +1078,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
                         syB += (ks1[sh] * (C)dy) * n.y;
                     }
                     if (sh <= 1) {
-                        const C2 m = ringR[sl[dy + 2]][tid + 2 + dx];
+                        const C2 m = ringR[sl[dy + 2]][cn];
                         const C kk = (sh == 0) ? kx1 : kx2;
                         if (dx != 0) { cxA += (kk * (C)dx) * m.y; cxB += (kk * (C)dx) * m.x; }
                         if (dy != 0) { cyA += (kk * (C)dy) * m.y; cyB += (kk * (C)dy) * m.x; }
@@ -1094,8 +1087,8 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
                 asm volatile("" : "+v"(sxA), "+v"(syA), "+v"(sxB), "+v"(syB), "+v"(cxA), "+v"(cyA),
                              "+v"(cxB), "+v"(cyB)::"memory");
             }
-            const C2 p0 = ringP[sl[2]][tid + 2];
-            const C2 r0c = ringR[sl[2]][tid + 2];
+            const C2 p0 = ringP[sl[2]][tid];
+            const C2 r0c = ringR[sl[2]][tid];
             const C ra = rref0 + r0c.x, rb = rref1 + r0c.y;
             const C pa = pref0 + p0.x, pb = pref1 + p0.y;
             const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
@@ -1103,7 +1096,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
             const C inv_rho = rcp(ra + rb);
             const C ux = J.x * inv_rho, uy = J.y * inv_rho;
             const C gx = (body != nullptr) ? (C)body[y] * inv_rho : (C)0;
-            if (prof != nullptr && x0 + 64 * wave < nx) {
+            if (prof != nullptr) {
                 double su = valid ? (double)ux : 0.0;
                 su = wave_sum(su);
                 if ((tid & 63) == 0) profS[wave * d.ly + (y - y0)] = su;
@@ -1195,10 +1188,11 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         if (valid && walls && y1 == ny) stress[nx + xc] += (double)mom_t;
         __syncthreads();
         if (prof != nullptr) {
-            const int nr = y1 - y0;
-            for (int e = tid; e < (BX / 64) * nr; e += BX) {
-                const int wv = e / nr, r = e % nr;
-                if (x0 + 64 * wv < nx) prof[(long long)(x0 / 64 + wv) * ny + y0 + r] += profS[wv * d.ly + r];
+            // one accumulator row per tile: the per-wave sums in wave order
+            for (int r = tid; r < y1 - y0; r += BX) {
+                double t = 0;
+                for (int wv = 0; wv < BX / 64; ++wv) t += profS[wv * d.ly + r];
+                prof[(long long)strip * ny + y0 + r] += t;
             }
         }
         __syncthreads();
