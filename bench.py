@@ -94,7 +94,9 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     256..1024, width 2H, U log-uniform in [1e-4, 5e-2], G^r in [7.5, 8.5]):
     one persistent step kernel per time step for the whole batch, replayed as
     HIP graphs, against the plain loop (one lattice at a time, one launch per
-    step, no graph).  Both produce the same per-lattice stresses."""
+    step, no graph).  Both produce the same per-lattice stresses.  The batch is
+    also run in the moment form (tau = 1); its stresses are compared with the
+    FP32 population batch."""
     from paper_1004_5058_amd import flowcurve, inputs, lb
     draws = inputs.ensemble(n_lat, seed=seed)
     specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
@@ -110,7 +112,21 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     rows_p, wall_p = flowcurve.run_plain(specs, steps)
     print(f"# flow curve: plain loop in {wall_p:.2f} s", file=sys.stderr, flush=True)
     agree = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_b, rows_p))
+    # the same ensemble in the moment form (tau = 1), batched, tuned shape
+    if tune_cache is not None:
+        b = lb.Batch(specs, storage="mom32", profile=True)
+        tm = b.autotune(tune_cache, steps=3)
+        b.close()
+    else:
+        tm = (0, 0, 0, 0.0)
+    rows_m, wall_m = flowcurve.run_batched(specs, steps, storage="mom32", bx=tm[0], ly=tm[1], grid=tm[2])
+    print(f"# flow curve: batched moment form in {wall_m:.2f} s", file=sys.stderr, flush=True)
+    agree_m = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_m, rows_b))
     return dict(lattices=n_lat, steps=steps, sites=sites,
+                batched_mom_points_per_hour=round(n_lat * 3600.0 / wall_m, 1), batched_mom_s=round(wall_m, 3),
+                batched_mom_mlups=round(sites * steps / wall_m / 1e6, 1),
+                mom_vs_f32_max_sigma_rel=float(f"{agree_m:.3e}"),
+                mom_launch_shape={"bx": tm[0], "ly": tm[1], "grid": tm[2]},
                 batched_points_per_hour=round(n_lat * 3600.0 / wall_b, 1),
                 plain_points_per_hour=round(n_lat * 3600.0 / wall_p, 1),
                 batched_s=round(wall_b, 3), plain_s=round(wall_p, 3),
