@@ -63,12 +63,21 @@ typedef enum {
     LB_ESTATE = -5       /* call out of order (e.g. load of a checkpoint of another shape) */
 } lb_status;
 
-/* Storage precision of the populations.  Every format stores the deviation
- * d_is = f_is - w_i rho_ref_s from the rest equilibrium at the reference
- * densities, rounded to nearest-even, and the step computes on deviations
- * (density deviations, deviations of psi from psi(rho_ref)), so the rounding
- * error scales with the departure from the reference state rather than with
- * f itself.  Arithmetic is FP64 for LB_F64 and FP32 otherwise. */
+/* Storage of the state.  The population formats (LB_F64 .. LB_BF16DEV) store
+ * the deviation d_is = f_is - w_i rho_ref_s from the rest equilibrium at the
+ * reference densities, rounded to nearest-even, and the step computes on
+ * deviations (density deviations, deviations of psi from psi(rho_ref)), so the
+ * rounding error scales with the departure from the reference state rather
+ * than with f itself.  Arithmetic is FP64 for LB_F64 and FP32 otherwise.
+ *
+ * LB_MOM32 / LB_MOM64 (FP32 / FP64): the moment form, valid only at tau = 1
+ * (lb_params.tau must be exactly 1; anything else is LB_EINVAL).  With tau = 1
+ * the BGK collision of Eq. (1) replaces every population by the equilibrium at
+ * the shifted velocity, so the post-collision state is the six moments
+ * (rho_s - rho_ref_s, v_s) per site; each step rebuilds the incoming
+ * populations from their source sites.  Same recurrence, 6 loads and 6 stores
+ * per site instead of 36.  lb_populations, lb_fields and lb_sums return the
+ * same quantities as for the population formats. */
 typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2, LB_BF16DEV = 3, LB_MOM32 = 4, LB_MOM64 = 5 } lb_storage;
 
 typedef struct {
