@@ -19,7 +19,8 @@ average duration, timed with HIP events on the lattice's stream.
 The launch shape comes from the project's autotuner (timed before the timed
 region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
 flow-curve points per hour on the batched 48-lattice ensemble (10 000 steps
-each) against a plain one-lattice-at-a-time loop.
+each) against a plain one-lattice-at-a-time loop; a third leg counts
+stress-controlled flow-curve points per hour with and without the surrogate.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--variants f32,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve] [--no-tune]
@@ -136,6 +137,51 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
                 launch_shape={"bx": tuned[0], "ly": tuned[1], "grid": tuned[2]})
 
 
+def surrogate_rates(n_train=512, n_cases=10):
+    """Stress-controlled flow-curve points per hour: the shear rate at which a
+    fixed-coupling lattice reaches a target wall stress, accepted when a
+    lattice run is within 1 % (the lattice judges every point).  Three ways:
+    the plain loop (bisection, one lattice run at a time), batched bisection
+    (one launch per step for all open cases), and batched with the surrogate
+    (network trained by the HIP kernels on a batched ensemble; the ensemble
+    and the training are charged to it)."""
+    from paper_1004_5058_amd import surrogate
+    G = surrogate.GAIN
+    nx, ny, steps, seed = G["nx"], G["ny"], G["steps"], G["seed"]
+    S_lo, S_hi = 2 * G["u"][0] / ny, 2 * G["u"][1] / ny
+
+    def lattice(batched):
+        return lambda pts: surrogate.lattice_stresses(pts, nx, ny, steps, seed, batched=batched)
+    t0 = time.perf_counter()
+    pts = surrogate.draw_points(n_train, 300, (S_lo, S_hi), G["g1"], G["g2"])
+    sig = lattice(True)(pts)
+    rows = [dict(g_aa1=g1, g_aa2=g2, S=S, sigma=v) for (g1, g2, S), v in zip(pts, sig)]
+    surr = surrogate.FlowSurrogate(max_rows=1024, seed=0)
+    surr.fit(rows, iters=4000, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    cases = surrogate.draw_points(n_cases, 31, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
+    targets = lattice(True)(cases)
+    out = dict(lattice=f"{nx}x{ny}", steps=steps, cases=n_cases, train_lattices=n_train,
+               train_s=round(t_train, 2))
+    for name, method, batched in (("plain", "bisect", False), ("batched", "bisect", True),
+                                  ("batched_surrogate", "surrogate", True)):
+        t0 = time.perf_counter()
+        solvers, rounds = surrogate.stress_controlled_points(cases, targets, method, lattice(batched), S_lo, S_hi,
+                                                             surr=surr)
+        wall = time.perf_counter() - t0
+        if method == "surrogate":
+            wall_all = wall + t_train
+        else:
+            wall_all = wall
+        ok = sum(s.result is not None for s in solvers)
+        out[name] = dict(lattice_runs=sum(s.runs for s in solvers), accepted=ok, wall_s=round(wall_all, 2),
+                         points_per_hour=round(ok * 3600.0 / wall_all, 1))
+        if method == "surrogate":
+            out[name]["wall_s_without_training"] = round(wall, 2)
+        print(f"# stress-controlled points, {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(n, steps=3, u=0.02, seed=1):
     """The FP64 oracle on the same 4096^2 workload, a bounded number of steps."""
     from oracle import oracle as O
@@ -163,6 +209,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flowcurve", action="store_true", help="skip the batched-vs-plain flow-curve leg")
     ap.add_argument("--flow-steps", type=int, default=10000)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the stress-controlled surrogate leg")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"))
     ap.add_argument("--calib-copy", action="store_true",
@@ -230,6 +277,11 @@ def main():
             print(f"# flow curve: {line['flowcurve']}", file=sys.stderr, flush=True)
         except Exception as e:  # reported, never hidden
             line["flowcurve"] = {"error": repr(e)}
+    if not a.no_flowcurve and not a.no_surrogate:
+        try:
+            line["surrogate"] = surrogate_rates()
+        except Exception as e:  # reported, never hidden
+            line["surrogate"] = {"error": repr(e)}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)

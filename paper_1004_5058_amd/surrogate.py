@@ -248,3 +248,51 @@ def solve_batched(solvers, lb_eval_many):
         for (k, _), v in zip(todo, sig):
             solvers[k].update(v)
         rounds += 1
+
+
+def lattice_stresses(points, nx, ny, steps, seed, storage="f32", batched=True):
+    """Time-averaged wall stress of fixed-coupling Couette lattices at
+    (g1, g2, S) points, all started from the same seeded emulsion: one batch
+    (one launch per step for all lattices), or one lattice at a time (the
+    plain loop)."""
+    draws = [dict(nx=nx, ny=ny, u_wall=S * ny / 2.0, g_aa1=g1, g_bb1=g1, g_aa2=g2, g_bb2=g2, seed=seed)
+             for g1, g2, S in points]
+    specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
+    if batched:
+        rows, _ = flowcurve.run_batched(specs, steps, storage=storage)
+    else:
+        rows, _ = flowcurve.run_plain(specs, steps, storage=storage)
+    return [r["sigma"] for r in rows]
+
+
+def stress_controlled_points(cases, targets, method, lb_eval_many, S_lo, S_hi, surr=None, tol=0.01):
+    """Run one solver per case (g1, g2, _) towards its target stress, in
+    lockstep rounds through lb_eval_many; returns (solvers, rounds)."""
+    solvers = []
+    for (g1, g2, _), t in zip(cases, targets):
+        x0, sl, model = None, 1.0, None
+        if method == "surrogate":
+            x0, sl = surr.root(g1, g2, t, S_lo, S_hi)
+            model = surr.curve(g1, g2)
+        solvers.append(RateSolver(t, S_lo, S_hi, method=method, x0=x0, slope0=sl, tol=tol, model=model))
+    rounds = solve_batched(solvers, lambda todo: lb_eval_many([(cases[k][0], cases[k][1], S) for k, S in todo]))
+    return solvers, rounds
+
+
+# The stress-controlled setting the surrogate is trained and judged in: 256 x 128
+# Couette lattices, 20000 steps, common seeded start, couplings straddling the
+# edge of the emulsion region, wall speeds 6e-3 .. 6e-2.
+GAIN = dict(nx=256, ny=128, steps=20000, seed=7, g1=(-9.2, -9.0), g2=(7.9, 8.1), u=(6e-3, 6e-2))
+
+
+def draw_points(n, seed, s_range, g1_range, g2_range, max_sum=None):
+    """(g1, g2, S) draws: couplings uniform, S log-uniform; with max_sum,
+    draws above G^a + G^r = max_sum are moved onto it (the emulsion side)."""
+    rng = np.random.default_rng(seed)
+    g1 = rng.uniform(*g1_range, n)
+    g2 = rng.uniform(*g2_range, n)
+    if max_sum is not None:
+        over = g1 + g2 > max_sum
+        g2[over] -= (g1 + g2 - max_sum)[over]
+    S = np.exp(rng.uniform(np.log(s_range[0]), np.log(s_range[1]), n))
+    return list(zip(g1.tolist(), g2.tolist(), S.tolist()))

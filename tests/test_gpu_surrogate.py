@@ -23,33 +23,24 @@ import numpy as np
 import pytest
 
 from gpu_common import need_gpu
-from paper_1004_5058_amd import flowcurve, inputs, surrogate
+from paper_1004_5058_amd import surrogate
 
 pytestmark = pytest.mark.gpu
 
-NX, NY, STEPS, SEED = 256, 128, 20000, 7
-G1, G2 = (-9.2, -9.0), (7.9, 8.1)
-U = (6e-3, 6e-2)
+_G = surrogate.GAIN
+NX, NY, STEPS, SEED = _G["nx"], _G["ny"], _G["steps"], _G["seed"]
+G1, G2 = _G["g1"], _G["g2"]
+U = _G["u"]
 S_LO, S_HI = 2 * U[0] / NY, 2 * U[1] / NY
 
 
 def _lb(points):
     """Lattice stress at (g1, g2, S) points, one batch."""
-    draws = [dict(nx=NX, ny=NY, u_wall=S * NY / 2.0, g_aa1=g1, g_bb1=g1, g_aa2=g2, g_bb2=g2, seed=SEED)
-             for g1, g2, S in points]
-    rows, _ = flowcurve.run_batched(flowcurve.lattice_specs(draws, inputs.COUPLINGS), STEPS)
-    return [r["sigma"] for r in rows]
+    return surrogate.lattice_stresses(points, NX, NY, STEPS, SEED)
 
 
 def _draw(n, seed, s_range=(S_LO, S_HI), g1_range=G1, g2_range=G2, max_sum=None):
-    rng = np.random.default_rng(seed)
-    g1 = rng.uniform(*g1_range, n)
-    g2 = rng.uniform(*g2_range, n)
-    if max_sum is not None:                  # move draws into G^a + G^r <= max_sum
-        over = g1 + g2 > max_sum
-        g2[over] -= (g1 + g2 - max_sum)[over]
-    S = np.exp(rng.uniform(np.log(s_range[0]), np.log(s_range[1]), n))
-    return list(zip(g1.tolist(), g2.tolist(), S.tolist()))
+    return surrogate.draw_points(n, seed, s_range, g1_range, g2_range, max_sum)
 
 
 @pytest.fixture(scope="module")
@@ -83,19 +74,9 @@ def test_surrogate_saves_lattice_runs(trained):
     targets = _lb(cases)
     report = {}
     for method in ("bisect", "secant", "surrogate"):
-        solvers = []
-        for (g1, g2, _), t in zip(cases, targets):
-            x0, sl, model = None, 1.0, None
-            if method == "surrogate":
-                x0, sl = trained.root(g1, g2, t, S_LO, S_HI)
-                model = trained.curve(g1, g2)
-            solvers.append(surrogate.RateSolver(t, S_LO, S_HI, method=method, x0=x0, slope0=sl, tol=0.01,
-                                                model=model))
-
-        def many(todo):
-            return _lb([(cases[k][0], cases[k][1], S) for k, S in todo])
         t0 = time.perf_counter()
-        rounds = surrogate.solve_batched(solvers, many)
+        solvers, rounds = surrogate.stress_controlled_points(cases, targets, method, _lb, S_LO, S_HI,
+                                                            surr=trained)
         wall = time.perf_counter() - t0
         runs = [s.runs for s in solvers]
         ok = sum(s.result is not None for s in solvers)
