@@ -1029,6 +1029,12 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes)
     if (hd.storage != b->storage || hd.nx != a.p.nx || hd.ny != a.p.ny || hd.pitch != a.pitch ||
         hd.profile != a.p.profile)
         return fail(LB_ESTATE, "checkpoint of another lattice shape, storage or profile setting");
+    // the section sizes must be exactly this lattice's (they bound the copies below)
+    const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
+    const size_t sbb = 2ull * a.p.nx * sizeof(double);
+    const size_t pb = a.p.profile ? (size_t)a.ngroups * a.p.ny * sizeof(double) : 0;
+    if (hd.fbytes != fb || hd.sbytes != sbb || hd.pbytes != pb)
+        return fail(LB_ESTATE, "checkpoint section sizes do not match this lattice");
     if (bytes < sizeof hd + hd.fbytes + hd.sbytes + hd.pbytes) return fail(LB_EINVAL, "truncated checkpoint");
     const char* p = (const char*)buf;
     b->cur = 0;

@@ -52,42 +52,42 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, RSRC_WORD3);
 }
 
-template <class S> __device__ __forceinline__ S bload(rsrc_t r, unsigned voff, int soff);
-template <> __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, int soff)
+template <class S> __device__ __forceinline__ S bload(rsrc_t r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, unsigned soff)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)soff, 0));
 }
-template <> __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, int soff)
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, unsigned soff)
 {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    return __builtin_bit_cast(double, (u2)__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(double, (u2)__builtin_amdgcn_raw_buffer_load_b64(r, voff, (int)soff, 0));
 }
-template <> __device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, int soff)
+template <> __device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, unsigned soff)
 {
-    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, (int)soff, 0));
 }
-template <> __device__ __forceinline__ __bf16 bload<__bf16>(rsrc_t r, unsigned voff, int soff)
+template <> __device__ __forceinline__ __bf16 bload<__bf16>(rsrc_t r, unsigned voff, unsigned soff)
 {
-    return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, (int)soff, 0));
 }
 
-template <class S> __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned voff, int soff);
-template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, unsigned voff, int soff)
+template <class S> __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, (int)soff, 0);
 }
-template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff, int soff)
+template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff, unsigned soff)
 {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, (int)soff, 0);
 }
-template <> __device__ __forceinline__ void bstore<_Float16>(_Float16 v, rsrc_t r, unsigned voff, int soff)
+template <> __device__ __forceinline__ void bstore<_Float16>(_Float16 v, rsrc_t r, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, (int)soff, 0);
 }
-template <> __device__ __forceinline__ void bstore<__bf16>(__bf16 v, rsrc_t r, unsigned voff, int soff)
+template <> __device__ __forceinline__ void bstore<__bf16>(__bf16 v, rsrc_t r, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, (int)soff, 0);
 }
 
 // Load / store one deviation, converting between the storage and the
@@ -95,15 +95,15 @@ template <> __device__ __forceinline__ void bstore<__bf16>(__bf16 v, rsrc_t r, u
 // uniform by construction; readfirstlane states it, so a store under a
 // divergent branch does not become a per-lane loop.
 template <class P>
-__device__ __forceinline__ typename P::C ld(rsrc_t r, unsigned voff, int soff)
+__device__ __forceinline__ typename P::C ld(rsrc_t r, unsigned voff, unsigned soff)
 {
     return (typename P::C)bload<typename P::S>(r, voff, __builtin_amdgcn_readfirstlane(soff));
 }
 
 template <class P>
-__device__ __forceinline__ void st(rsrc_t r, unsigned voff, int soff, typename P::C v)
+__device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, typename P::C v)
 {
-    bstore<typename P::S>((typename P::S)v, r, voff, __builtin_amdgcn_readfirstlane(soff));
+    bstore<typename P::S>((typename P::S)v, r, voff, (unsigned)__builtin_amdgcn_readfirstlane((int)soff));
 }
 
 // The 18 populations of one site held in registers between the row load and
@@ -119,8 +119,8 @@ template <class P> struct Row<P, false> {
     // Planes are stored shifted in x by c_ix: population q of the lane's node
     // sits one column left (c_ix = +1: vl), in place (vc) or one column right
     // (c_ix = -1: vr).  so: uniform SGPR byte offset; v*: per-lane byte offsets.
-    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, int so,
-                                         int pbytes)
+    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, unsigned so,
+                                         unsigned pbytes)
     {
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
@@ -138,17 +138,17 @@ template <class P> struct Row<P, true> {
     {
         return (float)((q & 1) ? v[q >> 1].y : v[q >> 1].x);
     }
-    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, int so,
-                                         int pbytes)
+    __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, unsigned so,
+                                         unsigned pbytes)
     {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const int q0 = 2 * k, q1 = 2 * k + 1;
             const int c0 = CX[q0 % 9], c1 = CX[q1 % 9];
             v[k].x = bload<S>(q0 < 9 ? r0 : r1, c0 > 0 ? vl : (c0 < 0 ? vr : vc),
-                              __builtin_amdgcn_readfirstlane(so + (q0 % 9) * pbytes));
+                              (unsigned)__builtin_amdgcn_readfirstlane((int)(so + (q0 % 9) * pbytes)));
             v[k].y = bload<S>(q1 < 9 ? r0 : r1, c1 > 0 ? vl : (c1 < 0 ? vr : vc),
-                              __builtin_amdgcn_readfirstlane(so + (q1 % 9) * pbytes));
+                              (unsigned)__builtin_amdgcn_readfirstlane((int)(so + (q1 % 9) * pbytes)));
         }
     }
 };
@@ -290,7 +290,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const rsrc_t rout0 = make_rsrc(fout, sbytes), rout1 = make_rsrc(fout + sbytes, sbytes);
         const int es = (int)sizeof(S);
         const unsigned vc = xc * es, vp = xp * es, vm = xm * es;   // columns x, x+1, x-1
-        const int pbytes = (int)(plane * es), rbytes = pitch * es;
+        const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
         const bool dma_halo = DMA32 || (DMA16 && (nx % 2) == 0);
         // DMA lanes.  4-byte storage, lanes 0..3: halo column x0-2, x0-1,
         // x0+BX, x0+BX+1 and its left and right neighbours (byte offsets).
@@ -368,7 +368,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                         const unsigned vo = ro + ((DMA32 && cx > 0) ? vhl : ((DMA32 && cx < 0) ? vhr : vh));
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(
                             q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
-                            __builtin_amdgcn_readfirstlane((q % 9) * pbytes), 0, 0);
+                            __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
                     }
                 }
             }
@@ -935,7 +935,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         const unsigned mbytes = (unsigned)(6 * plane * (long long)es);
         const rsrc_t rin = make_rsrc(base + d.off_f[src], mbytes);
         const rsrc_t rout = make_rsrc(base + d.off_f[src ^ 1], mbytes);
-        const int pbytes = (int)(plane * es), rbytes = pitch * es;
+        const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
         const unsigned vc = xc * es;
         const int cm = tid + 1;                           // the lane's moment-ring index
         // lanes 0 and 1 also load the two outer moment columns x0-3 and
@@ -954,7 +954,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         auto mrow_ok = [&](int r) { return !walls || (r >= 0 && r < ny); };
         auto mload = [&](MR& m, int r) {
             if (!mrow_ok(r)) return;
-            const int so = map_row<P>(r, ny, walls) * rbytes;
+            const unsigned so = (unsigned)map_row<P>(r, ny, walls) * rbytes;
 #pragma unroll
             for (int p = 0; p < 6; ++p) m.v[p] = ld<P>(rin, vc, so + p * pbytes);
             if (tid < 2) {
@@ -1105,7 +1105,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
             const C vAx = ux + (FxA * iA + gx), vAy = uy + FyA * iA;
             const C vBx = ux + (FxB * iB + gx), vBy = uy + FyB * iB;
             if (!valid) return;
-            const int so = y * rbytes;
+            const unsigned so = (unsigned)y * rbytes;
             st<P>(rout, vc, so, r0c.x);
             st<P>(rout, vc, so + pbytes, r0c.y);
             st<P>(rout, vc, so + 2 * pbytes, vAx);

@@ -116,3 +116,48 @@ def test_full_size_1024_against_oracle():
     e_s = max(abs(sb - osb / steps) / abs(osb / steps), abs(st - ost / steps) / abs(ost / steps))
     print(f"1024^2 FP32, {steps} steps: rho {e_rho:.2e}, j {e_j:.2e}, sigma {e_s:.2e}")
     assert e_rho < 1e-6 and e_j < 1e-6 and e_s < 1e-5
+
+
+def test_largest_class_fp32_windows():
+    """8192 x 8192 FP32: the per-species plane offsets exceed 2^31 bytes (the
+    direction-8 plane starts at 2.1 GB), the unsigned 32-bit buffer offsets
+    must still address them.  Sampled windows against the oracle after 3
+    steps, walls included."""
+    need_gpu()
+    from paper_1004_5058_amd import lb
+    n, u, k = 8192, 0.02, 3
+    m = 3 * k
+    ra, rb = inputs.emulsion(n, n, seed=2)
+    ux, uy = inputs.couette(n, n, u, -u)
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage="f32", **inputs.COUPLINGS)
+    lat.step(k)
+    ga, gb, gux, guy = lat.fields()
+    lat.close()
+    w = 20
+    for x0, y0, kind in [(5000, 3000, "interior"), (8190, 0, "bottom"), (100, n - (w + m), "top")]:
+        xs = np.arange(x0 - m, x0 + w + m) % n
+        if kind == "interior":
+            ys = slice(y0 - m, y0 + w + m)
+            p = oracle_params(w + 2 * m, w + 2 * m, False, 0, 0)
+            cut = (slice(m, m + w), slice(m, m + w))
+            gy = slice(y0, y0 + w)
+        elif kind == "bottom":
+            ys = slice(0, w + m)
+            p = oracle_params(w + 2 * m, w + m, True, u, -u)
+            cut = (slice(0, w), slice(m, m + w))
+            gy = slice(0, w)
+        else:
+            ys = slice(y0, n)
+            p = oracle_params(w + 2 * m, w + m, True, u, -u)
+            cut = (slice(m, m + w), slice(m, m + w))
+            gy = slice(n - w, n)
+        win = [np.ascontiguousarray(a[ys][:, xs]) for a in (ra, rb, ux, uy)]
+        f = O.init(p, *win)
+        g, _, _ = O.run(p, f, k)
+        oa, ob, oux, ouy = [a[cut] for a in O.fields(p, g)]
+        gxs = np.arange(x0, x0 + w) % n
+        sa, sb = ga[gy][:, gxs], gb[gy][:, gxs]
+        e_rho = max(np.max(np.abs(sa - oa)), np.max(np.abs(sb - ob)))
+        e_j = np.max(np.abs(gux[gy][:, gxs] * (sa + sb) - oux * (oa + ob))) / (1.1 * CS)
+        print(f"8192^2 {kind}: rho {e_rho:.2e}, j {e_j:.2e}")
+        assert e_rho < 1e-6 and e_j < 1e-6, (kind, e_rho, e_j)

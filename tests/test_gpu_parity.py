@@ -161,6 +161,16 @@ def test_checkpoint_resume_bitwise():
     np.testing.assert_array_equal(a.populations(), b.populations())
     assert a.stress() == b.stress()
     np.testing.assert_array_equal(a.profile()[0], b.profile()[0])
+    # a header whose section sizes disagree with the lattice is refused before
+    # anything is copied (the sizes bound the device copies)
+    from paper_1004_5058_amd import lb
+    for off in (48, 56, 64):          # fbytes, sbytes, pbytes (uint64 after the 48-byte prefix)
+        bad = ck.copy()
+        v = int.from_bytes(bad[off:off + 8].tobytes(), "little") + 256
+        bad[off:off + 8] = np.frombuffer(v.to_bytes(8, "little"), dtype=np.uint8)
+        with pytest.raises(lb.LBError, match="section sizes"):
+            b.load(bad)
+    assert b.time() == 51
 
 
 def test_batch_equals_single_lattices():
