@@ -182,7 +182,7 @@ def surrogate_rates(n_train=512, n_cases=10):
     return out
 
 
-def cpu_baseline(n, steps=3, u=0.02, seed=1):
+def cpu_baseline(n, steps=7, u=0.02, seed=1):
     """The FP64 oracle on the same 4096^2 workload, a bounded number of steps."""
     from oracle import oracle as O
     from paper_1004_5058_amd import inputs
