@@ -162,9 +162,11 @@ lb_status lb_sums(lb_handle* h, double out[5]);
  * LB_ENONFINITE. */
 lb_status lb_set_watchdog(lb_handle* h, int32_t every);
 
-/* Launch shape of the step kernel: bx threads per block (64, 128 or 256) =
- * lattice columns per tile, ly rows per tile (>= 1).  0 keeps the current
- * choice.  Results are bitwise independent of the shape. */
+/* Launch shape of the step kernel: bx threads per block (64, 128 or 256, and
+ * 512 for FP32 and 16-bit population storage) = lattice columns per tile, ly
+ * rows per tile (>= 1).  0 keeps the current choice.  LB_EINVAL for another
+ * bx or for a shape whose shared memory per block (it grows with bx and ly)
+ * exceeds the device's limit.  Results are bitwise independent of the shape. */
 lb_status lb_set_launch(lb_handle* h, int32_t bx, int32_t ly);
 
 /* HIP graph use in lb_step: steps per captured graph (0 = launch each step
@@ -179,7 +181,8 @@ lb_status lb_save(lb_handle* h, void* buf, size_t* bytes);
 lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
 
 /* Autotuner: times `steps` steps of every candidate launch shape (bx in
- * {64, 128, 256}, ly in {16..256}; for batches also persistent grids of 1, 2
+ * {64, 128, 256, 512} as lb_set_launch admits them, ly in {8..256}, shapes
+ * within the device's shared memory per block; for batches also persistent grids of 1, 2
  * and 4 blocks per compute unit) on this lattice, applies the fastest and
  * restores the simulation state exactly (populations, accumulators, step
  * count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid, ms}},

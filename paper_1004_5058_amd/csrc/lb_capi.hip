@@ -598,11 +598,47 @@ void default_shape(lbb_handle* h)
     }
 }
 
+// Tile widths with a step kernel: 64, 128, 256, and 512 for the FP32 and
+// 16-bit population forms.
+bool bx_supported(int storage, int bx)
+{
+    return bx == 64 || bx == 128 || bx == 256 || (bx == 512 && storage >= 1 && storage <= 3);
+}
+
+// LDS one step block needs for shape (bx, ly) on this batch, and whether the
+// current device grants it.
+size_t shape_lds(const lbb_handle* h, int bx, int ly)
+{
+    int maxny = 1;
+    for (const Lat& a : h->lats) maxny = std::max(maxny, a.p.ny);
+    return lbk::step_lds_bytes(h->storage, bx, std::min(std::min(ly, maxny), 256));
+}
+int device_lds_limit()
+{
+    int dev = 0, lim = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return lim;
+}
+bool shape_fits(const lbb_handle* h, int bx, int ly)
+{
+    const size_t need = shape_lds(h, bx, ly);
+    return need > 0 && need <= (size_t)device_lds_limit();
+}
+
 lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
 {
-    if (bx != 0 && bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "bx must be 64, 128 or 256");
+    if (bx != 0 && !bx_supported(h->storage, bx))
+        return fail(LB_EINVAL, "bx must be 64, 128 or 256 (or 512 for FP32 and 16-bit population storage)");
     if (ly < 0) return fail(LB_EINVAL, "ly must be >= 0");
     if (grid < 0) return fail(LB_EINVAL, "grid must be >= 0");
+    {
+        const int nbx = bx ? bx : h->bx, nly = ly ? ly : h->ly;
+        if (!shape_fits(h, nbx, nly))
+            return fail(LB_EINVAL, "launch shape bx %d ly %d needs %zu bytes of LDS per block, the device allows %d",
+                        nbx, nly, shape_lds(h, nbx, nly), device_lds_limit());
+    }
     if (bx) h->bx = bx;
     if (ly) h->ly = ly;
     h->grid = grid;
@@ -765,10 +801,11 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
         ncu = prop.multiProcessorCount;
     TuneEntry best;
     lb_status st = LB_OK;
-    for (int bx : {64, 128, 256}) {
-        if (bx > 64 && bx / 2 >= maxnx) continue;
+    for (int bx : {64, 128, 256, 512}) {
+        if (!bx_supported(h->storage, bx) || (bx > 64 && bx / 2 >= maxnx)) continue;
         for (int ly : {8, 16, 32, 48, 64, 80, 96, 128, 160, 192, 256}) {
             if (ly > 16 && ly / 2 >= maxny) continue;
+            if (!shape_fits(h, bx, ly)) continue;
             std::vector<int> grids = {0};
             if (batch)
                 for (int per : {1, 2, 4}) grids.push_back(ncu * per);

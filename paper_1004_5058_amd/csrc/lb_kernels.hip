@@ -210,11 +210,18 @@ __device__ __forceinline__ void lds_barrier()
 constexpr int LY_MAX = 256;
 
 // Dynamic LDS of the step kernel: the four halo columns of a segment
-// (rows y0-2 .. y1+1) and the per-wave row sums of u_x for the profile.
-template <class C>
+// (rows y0-2 .. y1+1), staged only by the formats without the direct-to-LDS
+// halo (4-byte storage always has it), and the per-wave row sums of u_x for
+// the profile.
+template <class P>
+__host__ __device__ constexpr size_t step_halo_lds(int ly)
+{
+    return sizeof(typename P::S) == 4 ? 0 : sizeof(typename P::C) * 4 * 4 * (size_t)(ly + 4);
+}
+template <class P>
 __host__ __device__ constexpr size_t step_dyn_lds(int bx, int ly)
 {
-    return sizeof(C) * 4 * 4 * (size_t)(ly + 4) + sizeof(double) * (size_t)(bx / 64) * ly;
+    return step_halo_lds<P>(ly) + sizeof(double) * (size_t)(bx / 64) * ly;
 }
 
 template <int BX, class P>
@@ -309,8 +316,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         double* __restrict__ stress = (double*)(base + d.off_stress);
         double* __restrict__ prof = d.off_prof >= 0 ? (double*)(base + d.off_prof) : nullptr;
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
-        C4* halo = (C4*)dyn_lds;                                       // [(ly + 4) * 4]
-        double* profS = (double*)(dyn_lds + sizeof(C4) * 4 * (d.ly + 4)); // [BX/64][ly]
+        C4* halo = (C4*)dyn_lds;                                     // [(ly + 4) * 4], unused by DMA32
+        double* profS = (double*)(dyn_lds + step_halo_lds<P>(d.ly));  // [BX/64][ly]
         C mom_b = 0, mom_t = 0;   // wall momentum of this thread's column, summed over the segment
 
         // 18 deviations of row r (any row; mapped through the walls or the
@@ -1367,7 +1374,7 @@ template <int BX, class P>
 static hipError_t step_bx(char* base, const LatDesc* descs, const int* tiles, int ntot, int src, int grid,
                           int ly, hipStream_t s)
 {
-    const size_t dyn = step_dyn_lds<typename P::C>(BX, ly);
+    const size_t dyn = step_dyn_lds<P>(BX, ly);
     hipLaunchKernelGGL((k_step<BX, P>), dim3(grid), dim3(BX), dyn, s, base, descs, tiles, ntot, src);
     return hipGetLastError();
 }
@@ -1380,6 +1387,9 @@ static hipError_t step_p(int bx, char* base, const LatDesc* descs, const int* ti
     case 64: return step_bx<64, P>(base, descs, tiles, ntot, src, grid, ly, s);
     case 128: return step_bx<128, P>(base, descs, tiles, ntot, src, grid, ly, s);
     case 256: return step_bx<256, P>(base, descs, tiles, ntot, src, grid, ly, s);
+    case 512:   // 4- and 2-byte storage only: halves the share of halo columns
+        if constexpr (sizeof(typename P::S) <= 4) return step_bx<512, P>(base, descs, tiles, ntot, src, grid, ly, s);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -1421,6 +1431,43 @@ static hipError_t step_mom_p(int bx, char* base, const LatDesc* descs, const int
     case 5: { using P = MomF64; return CALL; }                       \
     default: break;                                                  \
     }
+
+// LDS of one block: the kernel's static shared memory plus the dynamic part.
+template <class K>
+static size_t lds_of(K kernel, size_t dyn)
+{
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+    return fa.sharedSizeBytes + dyn;
+}
+
+size_t step_lds_bytes(int storage, int bx, int ly)
+{
+    switch (storage * 1000 + bx) {
+    case 0 * 1000 + 64: return lds_of(k_step<64, StF64>, step_dyn_lds<StF64>(64, ly));
+    case 0 * 1000 + 128: return lds_of(k_step<128, StF64>, step_dyn_lds<StF64>(128, ly));
+    case 0 * 1000 + 256: return lds_of(k_step<256, StF64>, step_dyn_lds<StF64>(256, ly));
+    case 1 * 1000 + 64: return lds_of(k_step<64, StF32>, step_dyn_lds<StF32>(64, ly));
+    case 1 * 1000 + 128: return lds_of(k_step<128, StF32>, step_dyn_lds<StF32>(128, ly));
+    case 1 * 1000 + 256: return lds_of(k_step<256, StF32>, step_dyn_lds<StF32>(256, ly));
+    case 1 * 1000 + 512: return lds_of(k_step<512, StF32>, step_dyn_lds<StF32>(512, ly));
+    case 2 * 1000 + 64: return lds_of(k_step<64, StF16>, step_dyn_lds<StF16>(64, ly));
+    case 2 * 1000 + 128: return lds_of(k_step<128, StF16>, step_dyn_lds<StF16>(128, ly));
+    case 2 * 1000 + 256: return lds_of(k_step<256, StF16>, step_dyn_lds<StF16>(256, ly));
+    case 2 * 1000 + 512: return lds_of(k_step<512, StF16>, step_dyn_lds<StF16>(512, ly));
+    case 3 * 1000 + 64: return lds_of(k_step<64, StBF16>, step_dyn_lds<StBF16>(64, ly));
+    case 3 * 1000 + 128: return lds_of(k_step<128, StBF16>, step_dyn_lds<StBF16>(128, ly));
+    case 3 * 1000 + 256: return lds_of(k_step<256, StBF16>, step_dyn_lds<StBF16>(256, ly));
+    case 3 * 1000 + 512: return lds_of(k_step<512, StBF16>, step_dyn_lds<StBF16>(512, ly));
+    case 4 * 1000 + 64: return lds_of(k_step_mom<64, MomF32>, mom_dyn_lds<MomF32::C>(64, ly));
+    case 4 * 1000 + 128: return lds_of(k_step_mom<128, MomF32>, mom_dyn_lds<MomF32::C>(128, ly));
+    case 4 * 1000 + 256: return lds_of(k_step_mom<256, MomF32>, mom_dyn_lds<MomF32::C>(256, ly));
+    case 5 * 1000 + 64: return lds_of(k_step_mom<64, MomF64>, mom_dyn_lds<MomF64::C>(64, ly));
+    case 5 * 1000 + 128: return lds_of(k_step_mom<128, MomF64>, mom_dyn_lds<MomF64::C>(128, ly));
+    case 5 * 1000 + 256: return lds_of(k_step_mom<256, MomF64>, mom_dyn_lds<MomF64::C>(256, ly));
+    default: return 0;
+    }
+}
 
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int first, int grid, int ly, hipStream_t s)

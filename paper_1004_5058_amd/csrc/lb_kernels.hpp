@@ -12,6 +12,9 @@ namespace lbk {
 // reads the local equilibria in place instead of pulling from neighbours).
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int first, int grid, int ly, hipStream_t s);
+// Shared memory (bytes) one step block needs for tile width bx and ly rows;
+// 0 if the storage has no step kernel of that width.
+size_t step_lds_bytes(int storage, int bx, int ly);
 hipError_t launch_init(int storage, char* base, const LatDesc* d, long long nsites, int buf,
                        const double* ra, const double* rb, const double* ux, const double* uy,
                        hipStream_t s);

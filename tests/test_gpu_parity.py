@@ -98,6 +98,44 @@ def test_tile_shape_bitwise(bx, ly):
     np.testing.assert_array_equal(lat.profile()[0], ref.profile()[0])
 
 
+@pytest.mark.parametrize("storage,nx,tol", [("f32", 700, 1e-7), ("f16dev", 700, 6e-5), ("bf16dev", 700, 5e-4),
+                                          ("f16dev", 701, 6e-5)])
+def test_wide_tiles_512(storage, nx, tol):
+    """512-column tiles (FP32 and 16-bit storage) with a ragged last strip:
+    oracle parity, and bitwise the 256-column result (stress and profile too)."""
+    ny, u = 90, 0.02
+    ra, rb = inputs.noise(nx, ny, seed=8)
+    p = oracle_params(nx, ny, True, u, -u)
+    g, _, _ = oracle_run(p, ra, rb, None, None, 60)
+    ref = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage, profile=True)
+    ref.set_launch(256, 32)
+    ref.step(60)
+    for ly in (32, 90, 7):
+        lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage, profile=True)
+        lat.set_launch(512, ly)
+        lat.step(60)
+        compare_fields(lat, p, g, tol)
+        np.testing.assert_array_equal(lat.populations(), ref.populations())
+        assert lat.stress() == ref.stress()
+        np.testing.assert_array_equal(lat.profile()[0], ref.profile()[0])
+        lat.close()
+
+
+def test_wide_tiles_rejected_without_a_kernel():
+    """FP64 and the moment form have no 512-column step: the shape is refused
+    and the lattice keeps stepping with its previous shape."""
+    from paper_1004_5058_amd import lb
+    ra, rb = inputs.noise(600, 40, seed=1)
+    for storage in ("f64", "mom32"):
+        ref = gpu_lattice(600, 40, ra, rb, storage=storage)
+        ref.step(3)
+        lat = gpu_lattice(600, 40, ra, rb, storage=storage)
+        with pytest.raises(lb.LBError, match="bx must be"):
+            lat.set_launch(512, 32)
+        lat.step(3)
+        np.testing.assert_array_equal(lat.populations(), ref.populations())
+
+
 def test_graph_replay_equals_direct_launch():
     nx, ny = 128, 64
     ra, rb = inputs.noise(nx, ny, seed=9, amp=0.05)
@@ -296,7 +334,7 @@ def test_autotune_preserves_state_and_caches(tmp_path):
     lat.step(4)
     cache = str(tmp_path / "tune.json")
     bx, ly, ms = lat.autotune(cache, steps=3)
-    assert bx in (64, 128, 256) and ly >= 8 and ms > 0
+    assert bx in (64, 128, 256, 512) and ly >= 8 and ms > 0
     assert lat.time() == 4
     lat.step(6)
     np.testing.assert_array_equal(lat.populations(), ref.populations())
