@@ -14,7 +14,11 @@ population step's.
 
 Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
 step (18 population loads + 18 stores per site) divided by the step kernel's
-average duration, timed with HIP events on the lattice's stream.
+average duration, timed with HIP events on the lattice's stream.  `hbm` adds
+the rate of the measured traffic (rocprofv3 counters, when taken on the
+current kernel source) and the live rate of a plain streaming copy on the same
+GPU.  `cpu_baseline` is the FP64 oracle on all host threads, with a
+single-thread rate beside it.
 
 The launch shape comes from the project's autotuner (timed before the timed
 region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
@@ -29,6 +33,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -199,6 +204,35 @@ def cpu_baseline(n, steps=7, u=0.02, seed=1):
                 sample=f"{steps} FP64 oracle steps of the full {n}x{n} lattice ({dt:.1f} s)")
 
 
+_SINGLE_THREAD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from paper_1004_5058_amd import inputs
+n, steps, u = int(sys.argv[2]), int(sys.argv[3]), 0.02
+ra, rb = inputs.emulsion(n, n, seed=1)
+ux, uy = inputs.couette(n, n, u, -u)
+p = O.OracleParams(nx=n, ny=n, walls=True, u_top=u, u_bot=-u, **inputs.COUPLINGS)
+f = O.init(p, ra, rb, ux, uy)
+t0 = time.perf_counter()
+O.run(p, f, steps)
+dt = time.perf_counter() - t0
+print(json.dumps({"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                  "sample": f"{steps} FP64 oracle steps of a {n}x{n} lattice of the same recipe ({dt:.1f} s)"}))
+"""
+
+
+def cpu_single_thread(n=1024, steps=3):
+    """The oracle on one thread, in a child process (OMP_NUM_THREADS=1; the
+    child never touches the GPU)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _SINGLE_THREAD, ROOT, str(n), str(steps)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +305,11 @@ def main():
     }
     for v in variants:
         line["variants"][v]["frac"] = round(line["variants"][v]["alg_gbs"] / HBM_PEAK_GBS, 4)
+    from paper_1004_5058_amd import lb
+    cp = lb.copy_peak()
+    line["hbm"] = {"measured_gbs": None if traffic is None else round(traffic / (r["ms_kernel"] * 1e-3) / 1e9, 1),
+                   "copy_peak_gbs": round(cp, 1), "frac_of_copy_peak": round(achieved / cp, 4),
+                   "copy": "library streaming copy, 16 B per lane, 2 GiB read + 2 GiB written"}
     if not a.no_flowcurve:
         try:
             line["flowcurve"] = flowcurve_rates(a.flow_steps, tune_cache=None if a.no_tune else a.tune_cache)
@@ -284,6 +323,7 @@ def main():
             line["surrogate"] = {"error": repr(e)}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n)
+        line["cpu_baseline"]["single_thread"] = cpu_single_thread()
     print(json.dumps(line), flush=True)
 
 

@@ -1195,12 +1195,10 @@ lb_status lb_copy_peak(void* dst, const void* src, size_t bytes, void* hip_strea
     if (!dst || !src || !gbs || reps < 1 || bytes < 16 || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return fail(LB_EINVAL, "copy needs 16-byte aligned buffers, a size multiple of 16 and reps >= 1");
     hipStream_t s = (hipStream_t)hip_stream;
-    int dev = 0, ncu = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-        ncu = prop.multiProcessorCount;
+    // full grid, one 16-byte element per thread: the fastest plain copy on
+    // this GPU (a grid-stride loop over a few blocks per CU is slower)
     const long long n16 = (long long)(bytes / 16);
-    const int blocks = (int)std::min<long long>((n16 + 255) / 256, (long long)ncu * 16);
+    const int blocks = (int)std::min<long long>((n16 + 255) / 256, 0x7fffffffLL);
     HIP_TRY(lbk::launch_copy(src, dst, n16, blocks, s));   // warm-up
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));

@@ -57,6 +57,30 @@ def test_fp32_parity_128_walls_100():
     _c1(steps=100, storage="f32", tol=1e-6)
 
 
+def test_error_growth_1_10_100():
+    """Error against the oracle after 1, 10 and 100 steps (128^2, walls +-0.01,
+    noise start, seed 0), FP64 and FP32: the growth is printed so that any
+    amplification of round-off shows, and every level is bounded."""
+    nx = ny = 128
+    u = 0.01
+    ra, rb = inputs.noise(nx, ny, 0)
+    p = oracle_params(nx, ny, True, u, -u)
+    snaps, g, t = {}, O.init(p, ra, rb), 0
+    for n in (1, 10, 100):
+        g, _, _ = O.run(p, g, n - t)
+        snaps[n], t = g, n
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-6)):
+        lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage)
+        t, row = 0, []
+        for n in (1, 10, 100):
+            lat.step(n - t)
+            t = n
+            e = compare_fields(lat, p, snaps[n], tol)
+            row.append(f"{n}: {max(e.values()):.2e}")
+        print(f"\n{storage} max field error after " + ", ".join(row))
+        lat.close()
+
+
 @pytest.mark.parametrize("nx,ny,walls", [(200, 77, True), (200, 77, False), (8, 8, True), (8, 5, False),
                                          (1, 6, True), (65, 3, True), (300, 130, True)])
 def test_fp64_parity_ragged(nx, ny, walls):
