@@ -249,7 +249,16 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
     __shared__ HT hst[(DMA32 || DMA16) ? 4 : 1][18][DMA16 ? 12 : 4];
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    // The halo work of row r (its direct-to-LDS loads and the halo densities)
+    // falls to wave r mod HW, so that it spreads over the SIMDs instead of
+    // gating every row's barrier on wave 0 (2-3 % on 16-bit storage).  Blocks
+    // of eight waves keep it on wave 0 (HW = 1), which measured faster there.
+    // The wave that issues a row's halo loads is the one that reads them back,
+    // and rows r and r + 4, which share a slot of the four-row halo ring, have
+    // the same halo wave: the prologue reuses slots without a barrier between.
+    constexpr int HW = BX / 64 <= 4 ? BX / 64 : 1;
+    auto halo_wave = [&](int r) { return r & (HW - 1); };
 
     for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
         const int L = tiles[w];          // owning lattice, -1 for alignment padding
@@ -299,15 +308,15 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const unsigned vc = xc * es, vp = xp * es, vm = xm * es;   // columns x, x+1, x-1
         const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
         const bool dma_halo = DMA32 || (DMA16 && (nx % 2) == 0);
-        // DMA lanes.  4-byte storage, lanes 0..3: halo column x0-2, x0-1,
+        // DMA lanes (of the row's halo wave).  4-byte storage, lanes 0..3: halo column x0-2, x0-1,
         // x0+BX, x0+BX+1 and its left and right neighbours (byte offsets).
         // 2-byte storage, lanes 0..5: the pair starts x0-4, x0-2, x0,
         // x0+BX-2, x0+BX, x0+BX+2.
         auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
         unsigned vh = 0, vhl = 0, vhr = 0;
-        if (tid < 6) {
-            const int hc = DMA16 ? ((tid < 3) ? x0 - 4 + 2 * tid : x0 + BX - 8 + 2 * tid)
-                                 : ((tid < 2) ? x0 - 2 + tid : x0 + BX + tid - 2);
+        if (lane < 6) {
+            const int hc = DMA16 ? ((lane < 3) ? x0 - 4 + 2 * lane : x0 + BX - 8 + 2 * lane)
+                                 : ((lane < 2) ? x0 - 2 + lane : x0 + BX + lane - 2);
             vh = (unsigned)wrap(hc) * es;
             vhl = (unsigned)wrap(hc - 1) * es;
             vhr = (unsigned)wrap(hc + 1) * es;
@@ -364,10 +373,11 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         }
         if (!dma_halo) lds_barrier();
 
-        // Issue the direct-to-LDS loads of row r's four halo columns (lanes 0..3).
+        // Issue the direct-to-LDS loads of row r's four halo columns (lanes 0..3 of
+        // the row's halo wave).
         auto halo_fetch = [&](int r) {
             if constexpr (DMA32 || DMA16) {
-                if (dma_halo && tid < ndma) {
+                if (dma_halo && wave == halo_wave(r) && lane < ndma) {
                     const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
 #pragma unroll
                     for (int q = 0; q < 18; ++q) {
@@ -384,10 +394,10 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         // the 12-element window row holds columns x0-4 .. x0+1 (elements 0..5)
         // and x0+BX-2 .. x0+BX+3 (6..11); halo column tid under shift c_ix is
         // element hb16 - c_ix (hb16: the unshifted element of the column).
-        const int hb16 = (tid < 2) ? 2 + tid : 6 + tid;
+        const int hb16 = (lane < 2) ? 2 + lane : 6 + lane;
         auto hval = [&](int r, int q) -> C {
             if constexpr (DMA32) {
-                return (C)__builtin_bit_cast(float, hst[r & 3][q][tid]);
+                return (C)__builtin_bit_cast(float, hst[r & 3][q][lane]);
             } else if constexpr (DMA16) {
                 return (C)__builtin_bit_cast(S, hst[r & 3][q][hb16 - CX[q % 9]]);
             } else {
@@ -396,7 +406,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         };
 
         // Stage row r (populations already in fr): (dpsi, drho) into the ring,
-        // plus the four halo entries (lanes 0..3).
+        // plus the four halo entries (lanes 0..3 of the row's halo wave).
         auto stage = [&](const R& fr, int r) {
             const int slot = __builtin_amdgcn_readfirstlane((r - y0 + 2) % 6);
             C da, db;
@@ -408,8 +418,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             rv.y = db;
             ringP[slot][tid + 2] = pv;
             ringR[slot][tid + 2] = rv;
-            if (tid < 4) {
-                const int hidx = (tid < 2) ? tid : BX + tid;
+            if (wave == halo_wave(r) && lane < 4) {
+                const int hidx = (lane < 2) ? lane : BX + lane;
                 C2 a, b;
                 if (dma_halo) {
                     // the row's own loads have completed (da, db above); the halo
@@ -426,7 +436,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                     b.x = ha;
                     b.y = hb;
                 } else {
-                    const C4 hv = halo[(r - y0 + 2) * 4 + tid];
+                    const C4 hv = halo[(r - y0 + 2) * 4 + lane];
                     a.x = hv.x;
                     a.y = hv.y;
                     b.x = hv.z;
