@@ -38,12 +38,11 @@ def _window(a, x0, y0, w, h):
     return np.ascontiguousarray(a[y0:y0 + h][:, xs])
 
 
-def test_sampled_windows_match_oracle(big):
-    lat, ra, rb, ux, uy, shape = big
-    k = 3
+def _check_windows(fields, ra, rb, ux, uy, k, tol, label):
+    """Interior, wrapped, bottom and top windows of the GPU fields after k steps
+    against the oracle run on each window with a 3k-site margin."""
     m = 3 * k
-    lat.step(k)
-    ga, gb, gux, guy = lat.fields()
+    ga, gb, gux, guy = fields
     w = 24
     cases = [(1000, 2000, "interior"), (4090, 17, "interior-wrap"), (77, 0, "bottom"), (2500, N - (w + m), "top")]
     for x0, y0, kind in cases:
@@ -73,8 +72,36 @@ def test_sampled_windows_match_oracle(big):
         e_rho = max(np.max(np.abs(sa - oa)), np.max(np.abs(sb - ob))) / 1.0
         e_j = max(np.max(np.abs(su * (sa + sb) - oux * (oa + ob))),
                   np.max(np.abs(sv * (sa + sb) - ouy * (oa + ob)))) / (1.1 * CS)
-        print(f"{kind} window at ({x0},{y0}), shape {shape}: rho {e_rho:.2e}, j {e_j:.2e}")
-        assert e_rho < 1e-6 and e_j < 1e-6, (kind, e_rho, e_j)
+        print(f"{label} {kind} window at ({x0},{y0}): rho {e_rho:.2e}, j {e_j:.2e}")
+        assert e_rho < tol and e_j < tol, (label, kind, e_rho, e_j)
+
+
+def test_sampled_windows_match_oracle(big):
+    lat, ra, rb, ux, uy, shape = big
+    lat.step(3)
+    _check_windows(lat.fields(), ra, rb, ux, uy, 3, 1e-6, f"f32 {shape}")
+
+
+# 16-bit deviation storage: every step (and the initialisation) rounds each
+# stored deviation to half an ulp.  With rho in [0.1, 1] around rho_ref ~ 0.55
+# the deviations are at most 0.2 (rest), 0.05 (axes), 0.0125 (diagonals), so
+# one rounding of the nine populations moves a density by at most
+# 6.1e-5 + 4 x 1.5e-5 + 4 x 3.8e-6 = 1.4e-4 in FP16; four roundings (init + 3
+# steps) give 5.5e-4, and the bound is taken at 1e-3 to cover the first-order
+# redistribution by the forces.  BF16 has an 8x coarser mantissa: 8e-3.
+@pytest.mark.parametrize("storage,tol", [("f16dev", 1e-3), ("bf16dev", 8e-3), ("mom32", 1e-6)])
+def test_other_storage_windows_in_bench_shape(big, storage, tol):
+    """The other storage forms the benchmark times, each in its own cached
+    launch shape, on the same windows."""
+    from paper_1004_5058_amd import lb
+    _, ra, rb, ux, uy, _ = big
+    lat = lb.Lattice(N, N, ra, rb, ux, uy, u_top=U, u_bot=-U, storage=storage, **inputs.COUPLINGS)
+    try:
+        bx, ly, _ = lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
+        lat.step(3)
+        _check_windows(lat.fields(), ra, rb, ux, uy, 3, tol, f"{storage} ({bx}, {ly})")
+    finally:
+        lat.close()
 
 
 def test_conservation_and_wall_budget(big):
