@@ -250,9 +250,9 @@ def main():
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported. "
-              "The path's sharding plan (y-slabs with halo rows, or whole lattices per GPU) "
-              "is described in the design notes.", file=sys.stderr)
+        print(f"bench.py: the library drives one GPU per process; --gpus {a.gpus} is not supported "
+              "(sharding by y-slabs with halo rows, or whole lattices per GPU, is not implemented).",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -5,7 +5,7 @@
  * mapping (G^a, G^r, log shear rate) of a lattice Boltzmann run to its mean
  * wall shear stress.  It is trained on points produced by batched lattice
  * runs (lbb_* in lb.h) and proposes where to refine a flow curve; the lattice
- * runs stay the judge of its error.
+ * runs remain the reference for its error.
  *
  * Inputs are standardised inside the kernels, x' = (x - in_mean)/in_std, and
  * the network's output is read on the standardised scale

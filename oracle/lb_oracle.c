@@ -24,8 +24,7 @@
  *                    (section "Numerical Results")
  *   5. streaming     f_is(r + c_i, t+1) = f*_is(r, t)             (Eq. (1), left)
  *
- * Readings of points the paper leaves open (each is listed with its reason in
- * the design notes):
+ * Readings of points the paper leaves open:
  *   - populations live on D2Q9; the 25-point two-belt set of Fig. 1 is the
  *     interaction stencil only (the paper ties c_S^2 and w_i to the D2Q9 set);
  *   - F^a and F^X use the D2Q9 weights on belt 1; F^r uses the two-belt weights

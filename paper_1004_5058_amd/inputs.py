@@ -6,7 +6,7 @@ parameters, from numpy's PCG64 generator with a fixed seed, so that both the
 GPU library and the CPU oracle start from byte-identical arrays.
 
 Workload recipes (the paper itself runs a 512x512 periodic box; these are the
-synthetic stand-ins of the same model, see the design notes):
+synthetic stand-ins of the same model):
   noise     rho_s = mean + U(-amp, amp), i.i.d. per site and species
   emulsion  per site a fair coin picks (rho_A, rho_B) = (major, minor) or
             (minor, major)

@@ -2,7 +2,7 @@
 mapping (G^a, G^r, log S) to the time-averaged wall stress of a Couette
 lattice, trained on points from batched lattice runs, used to propose where
 to refine a fixed-coupling flow curve near the yield stress.  Lattice runs
-check every proposal and stay the judge of the surrogate's error.
+check every proposal and remain the reference for the surrogate's error.
 
 The network regresses s = asinh(sigma / SIGMA_UNIT): close to log for
 stresses well above SIGMA_UNIT and linear through zero, so small and
