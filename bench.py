@@ -145,7 +145,7 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
 def surrogate_rates(n_train=512, n_cases=10):
     """Stress-controlled flow-curve points per hour: the shear rate at which a
     fixed-coupling lattice reaches a target wall stress, accepted when a
-    lattice run is within 1 % (the lattice judges every point).  Three ways:
+    lattice run is within 1 % (a lattice run checks every point).  Three ways:
     the plain loop (bisection, one lattice run at a time), batched bisection
     (one launch per step for all open cases), and batched with the surrogate
     (network trained by the HIP kernels on a batched ensemble; the ensemble

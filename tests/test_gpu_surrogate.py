@@ -2,7 +2,7 @@
 
 Each case asks for the shear rate at which a fixed-coupling Couette lattice
 reaches a target time-averaged wall stress (to 1 %).  Three solvers take
-lattice runs until one is within tolerance, so the lattice judges every
+lattice runs until one is within tolerance, so a lattice run checks every
 accepted point: bisection, a safeguarded secant without the network, and a
 search that starts at the network's root and then follows the network's
 curve shifted onto each lattice result.  The network is trained by the HIP
