@@ -100,7 +100,8 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     256..1024, width 2H, U log-uniform in [1e-4, 5e-2], G^r in [7.5, 8.5]):
     one persistent step kernel per time step for the whole batch, replayed as
     HIP graphs, against the plain loop (one lattice at a time, one launch per
-    step, no graph).  Both produce the same per-lattice stresses.  The batch is
+    step, no graph, each lattice size in its own tuned shape).  Both produce
+    the same per-lattice stresses.  The batch is
     also run in the moment form (tau = 1); its stresses are compared with the
     FP32 population batch."""
     from paper_1004_5058_amd import flowcurve, inputs, lb
@@ -115,7 +116,7 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
         tuned = (0, 0, 0, 0.0)
     rows_b, wall_b = flowcurve.run_batched(specs, steps, bx=tuned[0], ly=tuned[1], grid=tuned[2])
     print(f"# flow curve: batched {n_lat} lattices x {steps} steps in {wall_b:.2f} s", file=sys.stderr, flush=True)
-    rows_p, wall_p = flowcurve.run_plain(specs, steps)
+    rows_p, wall_p = flowcurve.run_plain(specs, steps, tune_cache=tune_cache)
     print(f"# flow curve: plain loop in {wall_p:.2f} s", file=sys.stderr, flush=True)
     agree = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_b, rows_p))
     # the same ensemble in the moment form (tau = 1), batched, tuned shape

@@ -132,19 +132,38 @@ def run_batched(specs, steps, storage="f32", average_from=None, bx=0, ly=0, grid
     return rows, wall
 
 
-def run_plain(specs, steps, storage="f32", average_from=None):
+def run_plain(specs, steps, storage="f32", average_from=None, tune_cache=None):
     """The same runs one lattice at a time, one kernel launch per step, no
-    graph: the baseline the batched path is measured against."""
+    graph: the baseline the batched path is measured against.  With
+    tune_cache, every lattice size is autotuned once before the timed loop
+    (results cached in that JSON file) and each lattice runs in the shape of
+    its size; otherwise in the library's default shape."""
     import torch
     from . import lb
     if average_from is None:
         average_from = steps // 2
+
+    def kwargs(s):
+        return {k: v for k, v in s.items() if k not in ("nx", "ny", "rho_a", "rho_b", "ux", "uy")}
+
+    shapes = {}
+    if tune_cache is not None:
+        for s in specs:
+            key = (s["nx"], s["ny"])
+            if key in shapes:
+                continue
+            lat = lb.Lattice(s["nx"], s["ny"], s["rho_a"], s["rho_b"], s["ux"], s["uy"], storage=storage,
+                             profile=True, **kwargs(s))
+            lat.set_graph(0)
+            shapes[key] = lat.autotune(tune_cache, steps=10)[:2]
+            lat.close()
     t0 = time.perf_counter()
     rows = []
     for s in specs:
-        kw = {k: v for k, v in s.items() if k not in ("nx", "ny", "rho_a", "rho_b", "ux", "uy")}
         lat = lb.Lattice(s["nx"], s["ny"], s["rho_a"], s["rho_b"], s["ux"], s["uy"], storage=storage,
-                         profile=True, **kw)
+                         profile=True, **kwargs(s))
+        if shapes:
+            lat.set_launch(*shapes[(s["nx"], s["ny"])])
         lat.set_graph(0)
         lat.step(average_from)
         lat.stress_reset()
