@@ -13,8 +13,8 @@ moments per site, 48 bytes per update instead of 144).  Each variant's
 population step's.
 
 Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
-step (18 population loads + 18 stores per site) divided by the step kernel's
-average duration, timed with HIP events on the lattice's stream.  `hbm` adds
+step (18 population loads + 18 stores per site) divided by the device time per
+step, from HIP events recorded on the lattice's stream around the timed steps.  `hbm` adds
 the rate of the measured traffic (rocprofv3 counters, when taken on the
 current kernel source) and the live rate of a plain streaming copy on the same
 GPU.  `cpu_baseline` is the FP64 oracle on all host threads, with a
@@ -80,11 +80,11 @@ def gpu_run(storage, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat.step(steps)
+    # the timed region: `steps` steps bracketed by HIP events on the lattice's
+    # own stream (lb_time_steps), which give the device time per step
+    ms_kernel = lat.time_steps(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # device time per step kernel, HIP events on the lattice's stream
-    ms_kernel = lat.time_steps(max(steps // 2, 1))
     sb, st, ns = lat.stress()
     lat.close()
     del lat
