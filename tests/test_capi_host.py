@@ -73,6 +73,17 @@ def test_state_bytes_rejects_bad_sizes():
         lb.lb_state_bytes(lb.make_params(16384, 16384, storage="f64"))
 
 
+@pytest.mark.parametrize("storage,n", [("f64", 7680), ("f32", 10880), ("f16dev", 15424), ("mom32", 13376)])
+def test_largest_accepted_lattice(storage, n):
+    """The largest square lattice whose planes of one species (nine values,
+    six in the moment form) stay below 4 GiB of 32-bit buffer offsets is
+    accepted; the next size up (64 more columns and rows) is refused."""
+    from paper_1004_5058_amd import lb
+    assert lb.lb_state_bytes(lb.make_params(n, n, storage=storage)) > 0
+    with pytest.raises(lb.LBError, match="too large"):
+        lb.lb_state_bytes(lb.make_params(n + 64, n + 64, storage=storage))
+
+
 def test_state_bytes_layout_scales_with_storage():
     from paper_1004_5058_amd import lb
     b64 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f64"))

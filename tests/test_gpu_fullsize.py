@@ -188,3 +188,39 @@ def test_largest_class_fp32_windows():
         e_j = np.max(np.abs(gux[gy][:, gxs] * (sa + sb) - oux * (oa + ob))) / (1.1 * CS)
         print(f"8192^2 {kind}: rho {e_rho:.2e}, j {e_j:.2e}")
         assert e_rho < 1e-6 and e_j < 1e-6, (kind, e_rho, e_j)
+
+
+def test_largest_accepted_fp32_lattice():
+    """10880 x 10880 FP32, the largest square lattice the 32-bit buffer offsets
+    admit (the last plane of a species ends 0.8 % below 4 GiB): windows at the
+    top-right corner, where the offsets are largest, and at the bottom wall
+    against the oracle after 3 steps."""
+    need_gpu()
+    from paper_1004_5058_amd import lb
+    n, u, k = 10880, 0.02, 3
+    m = 3 * k
+    ra, rb = inputs.emulsion(n, n, seed=4)
+    ux, uy = inputs.couette(n, n, u, -u)
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage="f32", **inputs.COUPLINGS)
+    lat.step(k)
+    ga, gb, gux, _ = lat.fields()
+    lat.close()
+    w = 20
+    for x0, kind in [(n - w, "top"), (n - 7, "bottom")]:
+        xs = np.arange(x0 - m, x0 + w + m) % n
+        if kind == "top":
+            ys = slice(n - (w + m), n)
+            cut, gy = (slice(m, m + w), slice(m, m + w)), slice(n - w, n)
+        else:
+            ys = slice(0, w + m)
+            cut, gy = (slice(0, w), slice(m, m + w)), slice(0, w)
+        p = oracle_params(w + 2 * m, w + m, True, u, -u)
+        win = [np.ascontiguousarray(a[ys][:, xs]) for a in (ra, rb, ux, uy)]
+        g, _, _ = O.run(p, O.init(p, *win), k)
+        oa, ob, oux, _ = [a[cut] for a in O.fields(p, g)]
+        gxs = np.arange(x0, x0 + w) % n
+        sa, sb = ga[gy][:, gxs], gb[gy][:, gxs]
+        e_rho = max(np.max(np.abs(sa - oa)), np.max(np.abs(sb - ob)))
+        e_j = np.max(np.abs(gux[gy][:, gxs] * (sa + sb) - oux * (oa + ob))) / (1.1 * CS)
+        print(f"{n}^2 {kind} corner: rho {e_rho:.2e}, j {e_j:.2e}")
+        assert e_rho < 1e-6 and e_j < 1e-6, (kind, e_rho, e_j)
