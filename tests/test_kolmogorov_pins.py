@@ -110,21 +110,39 @@ def test_stress_profile_balances_the_force():
         1.22 / 6 * 0.1 * 2 * np.pi / 512, rel=1e-14)
 
 
+def _golden():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
 def test_paper_start_and_couplings():
-    ra, rb = K.initial_densities(512)
-    assert ra.shape == (512, 512)
-    assert ra.max() == pytest.approx(0.61 * 1.1, rel=1e-12) and rb.max() == pytest.approx(0.61 * 1.01, rel=1e-12)
-    assert K.PAPER_COUPLINGS == dict(tau=1.0, g_aa1=-9.0, g_aa2=8.1, g_bb1=-8.0, g_bb2=7.1, g_ab=0.045)
+    """The protocol's start, wavenumbers and couplings are the printed ones."""
+    g = _golden()
+    st, fc = g["initial_densities"], g["footnote_couplings"]
+    L = st["L"]
+    ra, rb = K.initial_densities(L)
+    assert ra.shape == (L, L)
+    y = np.arange(L)
+    k_in = st["k_in_L_over_pi"] * np.pi / L
+    np.testing.assert_allclose(ra[:, 0], st["mean"] * (1 + st["amp_A"] * np.sin(k_in * y)), rtol=1e-14)
+    np.testing.assert_allclose(rb[:, 0], st["mean"] * (1 + st["amp_B"] * np.sin(k_in * y)), rtol=1e-14)
+    assert K.wavenumber(L) == pytest.approx(st["k_f_L_over_pi"] * np.pi / L, rel=1e-15)
+    assert K.PAPER_COUPLINGS == dict(tau=fc["tau"], g_aa1=fc["G_a_AA"], g_aa2=fc["G_r_AA"], g_bb1=fc["G_a_BB"],
+                                     g_bb2=fc["G_r_BB"], g_ab=fc["G_r_AB"])
 
 
 def test_vft_fit_recovers_the_papers_parameters():
-    """1/R = A exp(B/(rho_c - rho0)) with the printed A = 3.51, B = 0.045,
-    rho_c = 0.867 over the paper's rho0 range is recovered exactly."""
-    rho0 = np.array([0.70, 0.75, 0.78, 0.80, 0.81, 0.83, 0.85, 0.86])
-    inv_R = 3.51 * np.exp(0.045 / (0.867 - rho0))
+    """1/R = A exp(B/(rho_c - rho0)) with the printed A, B, rho_c over the
+    paper's rho0 range is recovered exactly."""
+    v = _golden()["vft"]
+    lo, hi = v["rho0_range"]
+    rho0 = np.array([lo, 0.75, 0.78, 0.80, 0.81, 0.83, 0.85, 0.86])
+    assert rho0.max() < v["rho_c"] < hi
+    inv_R = v["A"] * np.exp(v["B"] / (v["rho_c"] - rho0))
     fit = K.vft_fit(rho0, inv_R)
-    assert fit["rho_c"] == pytest.approx(0.867, abs=1e-6)
-    assert fit["A"] == pytest.approx(3.51, rel=1e-4)
-    assert fit["B"] == pytest.approx(0.045, rel=1e-4)
+    assert fit["rho_c"] == pytest.approx(v["rho_c"], abs=1e-6)
+    assert fit["A"] == pytest.approx(v["A"], rel=1e-4)
+    assert fit["B"] == pytest.approx(v["B"], rel=1e-4)
     with pytest.raises(ValueError):
         K.vft_fit([0.7, 0.8], [1.0, 2.0])

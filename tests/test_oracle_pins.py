@@ -6,7 +6,9 @@ surface-tension combination, closed forms of the stencil sums on sinusoids,
 conservation laws, the exact single-phase Couette solution, symmetries, and an
 independent brute-force writing of the force and of the whole step.
 """
+import json
 import math
+import os
 from fractions import Fraction as Fr
 
 import numpy as np
@@ -80,10 +82,14 @@ def test_two_belt_weights_are_the_unique_isotropic_set_with_twelve_sevenths():
 
 
 def test_paper_surface_tension_couplings_positive():
-    """With the paper's footnote couplings G~_AA = -9 + (12/7) 8.1 = 171/35 and
-    G~_BB = -8 + (12/7) 7.1 are positive, the case the paper discusses."""
-    gt_aa = Fr(-9) + Fr(12, 7) * Fr(81, 10)
-    gt_bb = Fr(-8) + Fr(12, 7) * Fr(71, 10)
+    """With the paper's footnote couplings (tests/golden) G~_AA = -9 + (12/7) 8.1
+    = 171/35 and G~_BB = -8 + (12/7) 7.1 are positive, the case the paper
+    discusses."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+    fc = gold["footnote_couplings"]
+    ratio = Fr(gold["surface_tension_factor"]["value"])
+    gt_aa = Fr(str(fc["G_a_AA"])) + ratio * Fr(str(fc["G_r_AA"]))
+    gt_bb = Fr(str(fc["G_a_BB"])) + ratio * Fr(str(fc["G_r_BB"]))
     assert gt_aa == Fr(171, 35) and gt_aa > 0 and gt_bb > 0
 
 
