@@ -143,21 +143,22 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
                 launch_shape={"bx": tuned[0], "ly": tuned[1], "grid": tuned[2]})
 
 
-def surrogate_rates(n_train=512, n_cases=10):
+def surrogate_rates(n_train=512, n_cases=10, storage="f32", plain=True):
     """Stress-controlled flow-curve points per hour: the shear rate at which a
     fixed-coupling lattice reaches a target wall stress, accepted when a
     lattice run is within 1 % (a lattice run checks every point).  Three ways:
     the plain loop (bisection, one lattice run at a time), batched bisection
     (one launch per step for all open cases), and batched with the surrogate
     (network trained by the HIP kernels on a batched ensemble; the ensemble
-    and the training are charged to it)."""
+    and the training are charged to it).  `storage` is the lattice storage of
+    every run (the training ensemble, the targets and the solvers)."""
     from paper_1004_5058_amd import surrogate
     G = surrogate.GAIN
     nx, ny, steps, seed = G["nx"], G["ny"], G["steps"], G["seed"]
     S_lo, S_hi = 2 * G["u"][0] / ny, 2 * G["u"][1] / ny
 
     def lattice(batched):
-        return lambda pts: surrogate.lattice_stresses(pts, nx, ny, steps, seed, batched=batched)
+        return lambda pts: surrogate.lattice_stresses(pts, nx, ny, steps, seed, storage=storage, batched=batched)
     t0 = time.perf_counter()
     pts = surrogate.draw_points(n_train, 300, (S_lo, S_hi), G["g1"], G["g2"])
     sig = lattice(True)(pts)
@@ -167,10 +168,11 @@ def surrogate_rates(n_train=512, n_cases=10):
     t_train = time.perf_counter() - t0
     cases = surrogate.draw_points(n_cases, 31, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
     targets = lattice(True)(cases)
-    out = dict(lattice=f"{nx}x{ny}", steps=steps, cases=n_cases, train_lattices=n_train,
+    out = dict(lattice=f"{nx}x{ny}", storage=storage, steps=steps, cases=n_cases, train_lattices=n_train,
                train_s=round(t_train, 2))
-    for name, method, batched in (("plain", "bisect", False), ("batched", "bisect", True),
-                                  ("batched_surrogate", "surrogate", True)):
+    legs = ((("plain", "bisect", False),) if plain else ()) + (("batched", "bisect", True),
+                                                              ("batched_surrogate", "surrogate", True))
+    for name, method, batched in legs:
         t0 = time.perf_counter()
         solvers, rounds = surrogate.stress_controlled_points(cases, targets, method, lattice(batched), S_lo, S_hi,
                                                              surr=surr)
@@ -184,7 +186,7 @@ def surrogate_rates(n_train=512, n_cases=10):
                          points_per_hour=round(ok * 3600.0 / wall_all, 1))
         if method == "surrogate":
             out[name]["wall_s_without_training"] = round(wall, 2)
-        print(f"# stress-controlled points, {name}: {out[name]}", file=sys.stderr, flush=True)
+        print(f"# stress-controlled points ({storage}), {name}: {out[name]}", file=sys.stderr, flush=True)
     return out
 
 
