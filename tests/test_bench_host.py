@@ -1,0 +1,45 @@
+"""Host-side checks of bench.py's contract (no GPU needed): the one-GPU
+refusal, the counter summary being used only for the kernel source it was
+taken on, and the JSON keys a benchmark line carries."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    entry = {"bytes_per_step": 123, "kernel_hash": bench.kernel_source_hash()}
+    (prof / "traffic.json").write_text(json.dumps({"w/f32": entry, "w/f16dev": dict(entry, kernel_hash="0" * 16)}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the hash is of the real sources; only the summary's location moves
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: entry["kernel_hash"])
+    assert bench.measured_traffic("w", "f32") == 123
+    assert bench.measured_traffic("w", "f16dev") is None       # taken on another kernel source
+    assert bench.measured_traffic("w", "bf16dev") is None      # never measured
+
+
+def test_committed_counters_match_the_committed_kernels():
+    """profiles/traffic.json is regenerated whenever the step kernel changes."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    assert d["couette_emulsion_4096x4096/f32"]["kernel_hash"] == bench.kernel_source_hash()
+    assert bench.measured_traffic("couette_emulsion_4096x4096", "f32") > 0
+
+
+@pytest.mark.parametrize("storage,b", [("f32", 144), ("f16dev", 72), ("bf16dev", 72), ("mom32", 48), ("f64", 288)])
+def test_algorithmic_bytes_per_update(storage, b):
+    assert bench.BYTES_PER_LUP[storage] == b
