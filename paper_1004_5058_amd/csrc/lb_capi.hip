@@ -118,10 +118,11 @@ Layout plan(std::vector<Lat>& lats)
     L.off_part = align_up(sizeof(lbk::LatDesc) * n, ALIGN);
     L.off_res = L.off_part + align_up(sizeof(double) * 5 * lbk::sums_blocks(), ALIGN);
     // results: 5 sums + flag slot + 2 per lattice stress + profile staging handled in f buffers
-    // Item -> lattice table: at most ceil(nx/64) * ny items per lattice (the
-    // narrowest tile, one row per segment) plus 7 alignment slots each.
+    // Item -> lattice table: at most ceil(nx/60) * ny items per lattice (the
+    // narrowest tile collides 60 columns: 64 lanes of the moment form, whose
+    // tiles overlap by four; one row per segment) plus 7 alignment slots each.
     long long items = 0;
-    for (const auto& a : lats) items += (long long)((a.p.nx + 63) / 64) * a.p.ny + 7;
+    for (const auto& a : lats) items += (long long)((a.p.nx + 59) / 60) * a.p.ny + 7;
     L.max_items = (int)std::min<long long>(items, INT32_MAX);
     L.off_tiles = L.off_res + align_up(sizeof(double) * (8 + 2 * n), ALIGN);
     size_t off = L.off_tiles + align_up(sizeof(int32_t) * (size_t)L.max_items, ALIGN);

@@ -144,3 +144,24 @@ def test_conservation_periodic():
     s1 = lat.sums()
     assert abs(s1[0] - s0[0]) < 1e-11 * s0[0] and abs(s1[1] - s0[1]) < 1e-11 * s0[1]
     assert abs(s1[2] - s0[2]) < 1e-10 and abs(s1[3] - s0[3]) < 1e-10
+
+
+def test_narrowest_tiles_fit_the_item_table():
+    """64-lane moment-form tiles collide 60 columns: a 64-wide lattice takes
+    two strips, and with one-row segments the batch's item table must hold
+    them (it is sized for 60-column tiles)."""
+    from paper_1004_5058_amd import lb
+    nx, ny, u = 64, 24, 0.01
+    ra, rb = inputs.noise(nx, ny, 3)
+    p = oracle_params(nx, ny, True, u, -u)
+    g, _, _ = oracle_run(p, ra, rb, None, None, 20)
+    b = lb.Batch([dict(nx=nx, ny=ny, rho_a=ra, rho_b=rb, ux=None, uy=None, u_top=u, u_bot=-u)],
+                 storage="mom32", profile=False)
+    b.set_launch(64, 1, 0)
+    b.step(20)
+
+    class _M:
+        def fields(self):
+            return b.fields(0)
+    compare_fields(_M(), p, g, 1e-6)
+    b.close()

@@ -64,3 +64,57 @@ def test_random_configuration_matches_oracle(seed):
           f"{max(e.values()):.2e}, populations {ep:.2e}")
     assert ep <= 10 * tol
     lat.close()
+
+
+class _Member:
+    """One lattice of a batch, seen through the fields call the comparisons use."""
+
+    def __init__(self, batch, k):
+        self.batch, self.k = batch, k
+
+    def fields(self):
+        return self.batch.fields(self.k)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_batch_matches_oracle(seed):
+    """Batches of 2-7 lattices of random sizes, each with its own walls, tau,
+    couplings, wall speeds and body force, under a random tile shape,
+    persistent grid and graph length: every lattice against its own oracle
+    run after 30 steps."""
+    import torch
+    from paper_1004_5058_amd import lb
+    r = np.random.default_rng(5000 + seed)
+    storage = ("f64", "f32", "f16dev", "mom32")[seed % 4]
+    specs, cases = [], []
+    for k in range(int(r.integers(2, 8))):
+        nx, ny = int(r.integers(1, 260)), int(r.integers(2, 140))
+        walls = bool(r.integers(2))
+        kw = dict(tau=1.0 if storage == "mom32" else float(r.uniform(0.6, 1.8)), rho0=float(r.uniform(0.7, 0.9)),
+                  g_aa1=float(r.uniform(-10.0, -7.0)), g_aa2=float(r.uniform(6.0, 9.0)),
+                  g_bb1=float(r.uniform(-10.0, -7.0)), g_bb2=float(r.uniform(6.0, 9.0)),
+                  g_ab=float(r.uniform(0.0, 0.5)))
+        if r.integers(2):
+            kw.update(fx_amp=float(r.uniform(0.0, 1e-4)), fx_k=float(r.uniform(0.0, 1.0)))
+        u_top, u_bot = (float(r.uniform(-0.03, 0.03)), float(r.uniform(-0.03, 0.03))) if walls else (0.0, 0.0)
+        ra, rb = inputs.noise(nx, ny, 100 * seed + k)
+        specs.append(dict(nx=nx, ny=ny, rho_a=ra, rho_b=rb, ux=None, uy=None, walls=walls, u_top=u_top,
+                          u_bot=u_bot, **kw))
+        cases.append((oracle_params(nx, ny, walls, u_top, u_bot, **kw), ra, rb))
+    bx = int(r.choice([64, 128, 256] + ([512] if storage in ("f32", "f16dev") else [])))
+    ly = int(r.integers(1, 150))
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    grid = int(r.choice([0, ncu, 2 * ncu]))
+    graph = int(r.choice([0, 2, 8, 32]))
+    b = lb.Batch(specs, storage=storage, profile=False)
+    b.set_launch(bx, ly, grid)
+    b.set_graph(graph)
+    b.step(30)
+    worst = 0.0
+    for k, (p, ra, rb) in enumerate(cases):
+        g, _, _ = oracle_run(p, ra, rb, None, None, 30)
+        e = compare_fields(_Member(b, k), p, g, TOL[storage])
+        worst = max(worst, max(e.values()))
+    b.close()
+    print(f"\nbatch seed {seed}: {len(specs)} lattices {storage} shape {bx}x{ly} grid {grid} graph {graph}: "
+          f"worst {worst:.2e}")
