@@ -5,12 +5,15 @@ shear), random 50/50 emulsion start (rho 1.0 / 0.1 per site, seed 1) with the
 linear Couette velocity, symmetric couplings G^a = -9.0, G^r = 8.1 (both
 species), G_AB = 0.405, rho0 = 0.83, tau = 1.  A step is one full time step of
 both species: pseudo-potential, belt-1/two-belt forces, BGK collision,
-streaming, walls and the FP64 wall-stress accumulation.  Populations are FP32
-(headline `value`); FP16- and BF16-deviation storage are timed beside it, and
-so is the moment form ("mom32": at tau = 1 the post-collision state is six
-moments per site, 48 bytes per update instead of 144).  Each variant's
-`frac` is against its own byte floor; the roofline object is the FP32
-population step's.
+streaming, walls and the FP64 wall-stress accumulation.  Populations are FP32;
+the headline `value` runs them two steps per pass ("f32x2": one kernel keeps
+step t's populations on chip and runs step t+1 behind it, bitwise the result
+of single steps, so each population crosses HBM once per two updates); the
+single-step kernel ("f32"), FP16- and BF16-deviation storage and the moment
+form ("mom32": at tau = 1 six moments per site, 48 bytes per update) are timed
+beside it.  Each variant's `frac` uses the algorithmic bytes of one update in
+its storage (144 for FP32); f32x2 also reports its own floor (72 B per update).
+The roofline object is the headline variant's.
 
 Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
 step (18 population loads + 18 stores per site) divided by the device time per
@@ -41,7 +44,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72, "bf16dev": 72, "mom32": 48, "mom64": 96}
+# Algorithmic HBM bytes per 2-species lattice update: 18 population loads and
+# 18 stores in the storage format (the moment form: 6 + 6 moments).  "f32x2"
+# is FP32 storage run two steps per pass (lb_set_fusion); its roofline figure
+# keeps the per-update 144 B, while each population actually crosses HBM once
+# per two updates (FLOOR_PER_LUP).
+BYTES_PER_LUP = {"f64": 288, "f32": 144, "f32x2": 144, "f16dev": 72, "bf16dev": 72, "mom32": 48, "mom64": 96}
+FLOOR_PER_LUP = {"f32x2": 72}
+STEPS_PER_LAUNCH = {"f32x2": 2}
+
+
+def variant_storage(v):
+    return "f32" if v == "f32x2" else v
 
 
 def kernel_source_hash():
@@ -53,8 +67,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, storage):
-    """HBM bytes per step from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per kernel launch (a launch advances STEPS_PER_LAUNCH steps)
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -65,18 +80,20 @@ def measured_traffic(workload, storage):
     e = d.get(f"{workload}/{storage}")
     if not e or e.get("kernel_hash") != kernel_source_hash():
         return None
-    return e.get("bytes_per_step")
+    return e.get("bytes_per_launch", e.get("bytes_per_step"))
 
 
-def gpu_run(storage, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
+def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
     import torch
     from paper_1004_5058_amd import inputs, lb
     ra, rb = inputs.emulsion(n, n, seed=seed)
     ux, uy = inputs.couette(n, n, u, -u)
-    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=storage, profile=False,
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=variant_storage(variant), profile=False,
                      **inputs.COUPLINGS)
     del ra, rb, ux, uy
     shape = lat.autotune(tune_cache, steps=10) if tune_cache is not None else None
+    if STEPS_PER_LAUNCH.get(variant, 1) == 2:
+        lat.set_fusion(2)
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -242,7 +259,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--variants", default="f32,f16dev,bf16dev,mom32")
+    ap.add_argument("--variants", default="f32x2,f32,f16dev,bf16dev,mom32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flowcurve", action="store_true", help="skip the batched-vs-plain flow-curve leg")
     ap.add_argument("--flow-steps", type=int, default=10000)
@@ -293,9 +310,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if head == "f32" else head,
+        "dtype": variant_storage(head),
         "data": "synthetic (seeded emulsion start, linear Couette velocity)",
-        "config": {"workload": workload, "nx": n, "ny": n, "storage": head, "walls": "bounce-back +-0.02",
+        "config": {"workload": workload, "nx": n, "ny": n, "storage": variant_storage(head),
+                   "steps_per_pass": STEPS_PER_LAUNCH.get(head, 1), "walls": "bounce-back +-0.02",
                    "tau": 1.0, "rho0": 0.83, "G": [-9.0, 8.1, -9.0, 8.1, 0.405]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -308,9 +326,17 @@ def main():
     }
     for v in variants:
         line["variants"][v]["frac"] = round(line["variants"][v]["alg_gbs"] / HBM_PEAK_GBS, 4)
+        if v in FLOOR_PER_LUP:
+            fl = FLOOR_PER_LUP[v] * float(n) * n / (res[v]["ms_kernel"] * 1e-3) / 1e9
+            line["variants"][v]["floor_bytes_per_lup"] = FLOOR_PER_LUP[v]
+            line["variants"][v]["floor_gbs"] = round(fl, 1)
+            line["variants"][v]["frac_of_floor"] = round(fl / HBM_PEAK_GBS, 4)
     from paper_1004_5058_amd import lb
     cp = lb.copy_peak()
-    line["hbm"] = {"measured_gbs": None if traffic is None else round(traffic / (r["ms_kernel"] * 1e-3) / 1e9, 1),
+    per_launch = STEPS_PER_LAUNCH.get(head, 1)
+    line["hbm"] = {"measured_gbs": None if traffic is None
+                   else round(traffic / (per_launch * r["ms_kernel"] * 1e-3) / 1e9, 1),
+                   "steps_per_launch": per_launch,
                    "copy_peak_gbs": round(cp, 1), "frac_of_copy_peak": round(achieved / cp, 4),
                    "copy": "library streaming copy, 16 B per lane, 2 GiB read + 2 GiB written"}
     if not a.no_flowcurve:

@@ -173,6 +173,17 @@ lb_status lb_set_launch(lb_handle* h, int32_t bx, int32_t ly);
  * directly).  Default 32. */
 lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
 
+/* Time steps per pass of the step kernel over the populations: 1 (default)
+ * or 2.  With 2, lb_step advances pairs of steps (Eq. (1) applied twice) with
+ * one kernel that keeps the intermediate populations in on-chip memory, so
+ * each population crosses HBM once per two updates; an odd remaining step
+ * runs alone.  The results are bitwise those of single steps.  Tiles of 250
+ * columns x ly2 rows (ly2 = 0: the smallest height that leaves at most one
+ * tile per compute unit).  LB_EINVAL unless the storage is LB_F32, the
+ * profile accumulators are off and the device grants the kernel's shared
+ * memory (about 125 KiB per block). */
+lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
+
 /* Checkpoint: the populations in their storage format, the step count and
  * the FP64 stress/profile accumulators.  lb_save with buf = NULL reports the
  * size in *bytes.  Both synchronise.  lb_load requires a handle of the same
@@ -239,6 +250,8 @@ lb_status lbb_destroy(lbb_handle* h);
  * synchronises.  Used by the benchmark for the roofline figure. */
 lb_status lb_time_steps(lb_handle* h, int32_t nsteps, double* ms_per_step);
 lb_status lbb_time_steps(lbb_handle* h, int32_t nsteps, double* ms_per_step);
+/* lb_set_fusion for a batch. */
+lb_status lbb_set_fusion(lbb_handle* h, int32_t steps_per_pass, int32_t ly2);
 
 #ifdef __cplusplus
 }

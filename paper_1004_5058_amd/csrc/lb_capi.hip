@@ -106,8 +106,9 @@ struct Lat {
 // Layout: [descs][partials][results][item table] then per lattice
 // [f0][f1][stress][prof][body force per row].
 struct Layout {
-    size_t off_desc = 0, off_part = 0, off_res = 0, off_tiles = 0, total = 0;
+    size_t off_desc = 0, off_part = 0, off_res = 0, off_tiles = 0, off_tiles2 = 0, total = 0;
     int max_items = 0;   // capacity of the item -> lattice table (any launch shape)
+    int max_items2 = 0;  // the same for the fused two-step kernel's tiles
 };
 
 Layout plan(std::vector<Lat>& lats)
@@ -124,8 +125,13 @@ Layout plan(std::vector<Lat>& lats)
     long long items = 0;
     for (const auto& a : lats) items += (long long)((a.p.nx + 59) / 60) * a.p.ny + 7;
     L.max_items = (int)std::min<long long>(items, INT32_MAX);
+    // Fused two-step tiles: strips of TW2 columns, at most one row per segment.
+    long long items2 = 0;
+    for (const auto& a : lats) items2 += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * a.p.ny + 7;
+    L.max_items2 = (int)std::min<long long>(items2, INT32_MAX);
     L.off_tiles = L.off_res + align_up(sizeof(double) * (8 + 2 * n), ALIGN);
-    size_t off = L.off_tiles + align_up(sizeof(int32_t) * (size_t)L.max_items, ALIGN);
+    L.off_tiles2 = L.off_tiles + align_up(sizeof(int32_t) * (size_t)L.max_items, ALIGN);
+    size_t off = L.off_tiles2 + align_up(sizeof(int32_t) * (size_t)L.max_items2, ALIGN);
     for (auto& a : lats) {
         const size_t es = storage_size(a.p.storage);
         a.pitch = (int)align_up((size_t)a.p.nx, 64);
@@ -224,6 +230,9 @@ struct lbb_handle {
     int ntot = 0;
     int ly_max = 1;                  // largest rows-per-tile over the lattices
     int graph_steps = 32;
+    int fusion = 1;                  // time steps per step-kernel pass: 1, or 2 (k_step2)
+    int ly2 = 0;                     // rows per fused tile (0: about one tile per compute unit)
+    int ntot2 = 0;
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // graph starting from buffer 0 / 1
     int watchdog = 0;
     int flag_host = 0;
@@ -232,7 +241,9 @@ struct lbb_handle {
     int* d_flag() { return (int*)(base + lay.off_res + 6 * sizeof(double)); }
     lbk::LatDesc* d_desc() { return (lbk::LatDesc*)(base + lay.off_desc); }
     int32_t* d_tiles() { return (int32_t*)(base + lay.off_tiles); }
+    int32_t* d_tiles2() { return (int32_t*)(base + lay.off_tiles2); }
     std::vector<int32_t> tiles;      // host copy of the item -> lattice table
+    std::vector<int32_t> tiles2;     // the same for the fused two-step tiles
 };
 
 struct lb_handle {
@@ -276,9 +287,49 @@ lb_status decompose(lbb_handle* h)
     }
     if (item > h->lay.max_items) return fail(LB_EINVAL, "launch shape gives more work items than planned");
     h->ntot = item;
+    // Fused two-step tiles: TW2 columns x ly2 rows.  ly2 = 0 picks the
+    // smallest height that leaves at most one tile per compute unit.
+    int ly2 = h->ly2;
+    if (ly2 <= 0) {
+        int dev = 0, ncu = 256, maxny = 1;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ncu = prop.multiProcessorCount;
+        long long rows = 0;
+        for (const Lat& a : h->lats) {
+            rows += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * a.p.ny;
+            maxny = std::max(maxny, a.p.ny);
+        }
+        ly2 = (int)std::max<long long>(16, (rows + ncu - 1) / ncu);
+        for (; ly2 < maxny; ++ly2) {
+            long long it = 0;
+            for (const Lat& a : h->lats)
+                it += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * ((a.p.ny + ly2 - 1) / ly2);
+            if (it <= ncu) break;
+        }
+    }
+    int item2 = 0;
+    h->tiles2.clear();
+    for (size_t k = 0; k < h->lats.size(); ++k) {
+        const Lat& a = h->lats[k];
+        lbk::LatDesc& d = h->descs[k];
+        d.nstrip2 = (a.p.nx + lbk::TW2 - 1) / lbk::TW2;
+        d.ly2 = std::min(ly2, a.p.ny);
+        d.nseg2 = (a.p.ny + d.ly2 - 1) / d.ly2;
+        d.nitems2 = d.nstrip2 * d.nseg2;
+        item2 = (item2 + 7) / 8 * 8;
+        d.item_begin2 = item2;
+        item2 += d.nitems2;
+        h->tiles2.resize(d.item_begin2, -1);
+        h->tiles2.resize(item2, (int32_t)k);
+    }
+    if (item2 > h->lay.max_items2) return fail(LB_EINVAL, "fused tile height gives more work items than planned");
+    h->ntot2 = item2;
     HIP_TRY(hipMemcpyAsync(h->d_desc(), h->descs.data(), sizeof(lbk::LatDesc) * h->descs.size(),
                            hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(h->d_tiles(), h->tiles.data(), sizeof(int32_t) * h->tiles.size(),
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_tiles2(), h->tiles2.data(), sizeof(int32_t) * h->tiles2.size(),
                            hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     drop_graphs(h);
@@ -299,15 +350,31 @@ lb_status launch_one(lbb_handle* h, hipStream_t s, int src, int first = 0)
     return LB_OK;
 }
 
+// Steps t and t+1 in one launch: reads buffer src, writes buffer src ^ 1.
+lb_status launch_two(lbb_handle* h, hipStream_t s, int src)
+{
+    hipError_t e = lbk::launch_step2(h->storage, h->base, h->d_desc(), h->d_tiles2(), h->ntot2, src,
+                                     std::max(1, h->ntot2), s);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "fused step launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
 lb_status build_graph(lbb_handle* h, int start)
 {
     if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
     lb_status st = LB_OK;
     int src = start;
-    for (int k = 0; k < h->graph_steps && st == LB_OK; ++k) {
-        st = launch_one(h, h->capture, src);
-        src ^= 1;
+    if (h->fusion == 2) {
+        for (int k = 0; k < h->graph_steps / 2 && st == LB_OK; ++k) {
+            st = launch_two(h, h->capture, src);
+            src ^= 1;
+        }
+    } else {
+        for (int k = 0; k < h->graph_steps && st == LB_OK; ++k) {
+            st = launch_one(h, h->capture, src);
+            src ^= 1;
+        }
     }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->capture, &g);
@@ -359,14 +426,32 @@ lb_status steps(lbb_handle* h, int32_t n)
                 lb_status st = build_graph(h, h->cur);
                 if (st != LB_OK) return st;
             }
-            for (int r = 0; r < reps; ++r)
+            for (int r = 0; r < reps; ++r) {
                 HIP_TRY(hipGraphLaunch(h->exec[h->cur], h->stream));
-            // graph_steps is even, so the buffer parity is unchanged
+                // graph_steps is even: single steps leave the buffer parity
+                // unchanged, fused pairs flip it once per pair
+                if (h->fusion == 2 && ((h->graph_steps / 2) & 1)) {
+                    h->cur ^= 1;
+                    if (r + 1 < reps && !h->exec[h->cur]) {
+                        lb_status st = build_graph(h, h->cur);
+                        if (st != LB_OK) return st;
+                    }
+                }
+            }
             const int done = reps * h->graph_steps;
             h->t += done;
             h->nsamples += done;
             n -= done;
             chunk -= done;
+        }
+        if (h->fusion == 2) {
+            for (; chunk >= 2; chunk -= 2, n -= 2) {
+                lb_status st = launch_two(h, h->stream, h->cur);
+                if (st != LB_OK) return st;
+                h->cur ^= 1;
+                h->t += 2;
+                h->nsamples += 2;
+            }
         }
         for (int k = 0; k < chunk; ++k) {
             lb_status st = launch_one(h, h->stream, h->cur);
@@ -646,6 +731,30 @@ lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
     return decompose(h);
 }
 
+// Two time steps per pass (k_step2): FP32 population storage, no profile
+// accumulators.  ly2 = 0 picks the tile height.  (The kernel is also built for
+// 16-bit storage, where it measured slower than single steps.)
+lb_status set_fusion(lbb_handle* h, int k, int ly2)
+{
+    if (k != 1 && k != 2) return fail(LB_EINVAL, "steps per pass must be 1 or 2");
+    if (ly2 < 0) return fail(LB_EINVAL, "ly2 must be >= 0");
+    if (k == 2) {
+        if (h->storage != LB_F32) return fail(LB_EINVAL, "two steps per pass need FP32 population storage");
+        for (const Lat& a : h->lats)
+            if (a.p.profile) return fail(LB_EINVAL, "two steps per pass keep no profile accumulators");
+        int dev = 0, lim = 65536;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const size_t need = lbk::step2_lds_bytes(h->storage);
+        if (need == 0 || need > (size_t)lim)
+            return fail(LB_EINVAL, "two steps per pass need %zu bytes of LDS per block, the device allows %d", need,
+                        lim);
+    }
+    h->fusion = k;
+    h->ly2 = ly2;
+    return decompose(h);
+}
+
 lb_status steps_direct_warm(lbb_handle* h, int n)
 {
     for (int k = 0; k < n; ++k) {
@@ -791,8 +900,10 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     const int cur = h->cur;
     const int64_t t = h->t, ns = h->nsamples;
     const int bx0 = h->bx, ly0 = h->ly, grid0 = h->grid, gs0 = h->graph_steps, wd0 = h->watchdog;
+    const int fu0 = h->fusion;
     h->graph_steps = 0;
     h->watchdog = 0;
+    h->fusion = 1;          // the single-step kernel's shapes are what is tuned
 
     int maxnx = 0, maxny = 0;
     for (const Lat& a : h->lats) { maxnx = std::max(maxnx, a.p.nx); maxny = std::max(maxny, a.p.ny); }
@@ -838,6 +949,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     h->t = t;
     h->nsamples = ns;
     h->graph_steps = gs0;
+    h->fusion = fu0;
     h->watchdog = wd0;
     if (st != LB_OK) {
         (void)set_launch(h, bx0, ly0, grid0);
@@ -999,6 +1111,12 @@ lb_status lb_set_launch(lb_handle* h, int32_t bx, int32_t ly)
 {
     CHECK_H(h);
     return set_launch(&h->b, bx, ly, 0);
+}
+
+lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2)
+{
+    CHECK_H(h);
+    return set_fusion(&h->b, steps_per_pass, ly2);
 }
 
 lb_status lb_set_graph(lb_handle* h, int32_t k)
@@ -1174,6 +1292,12 @@ lb_status lbb_set_launch(lbb_handle* h, int32_t bx, int32_t ly, int32_t grid)
 {
     CHECK_H(h);
     return set_launch(h, bx, ly, grid);
+}
+
+lb_status lbb_set_fusion(lbb_handle* h, int32_t steps_per_pass, int32_t ly2)
+{
+    CHECK_H(h);
+    return set_fusion(h, steps_per_pass, ly2);
 }
 
 lb_status lbb_set_graph(lbb_handle* h, int32_t k)

@@ -20,6 +20,9 @@ struct LatDesc {
     int nitems;            // nstrip * nseg
     int nstrip, nseg, ly;  // tiles: strips of bx columns, segments of ly rows
     int ngroups;           // ceil(nx / 64)
+    // Tiles of the fused two-step kernel: strips of 250 columns, segments of
+    // ly2 rows, items item_begin2 .. item_begin2 + nitems2 - 1 of its own table.
+    int item_begin2, nitems2, nstrip2, nseg2, ly2;
     double tau, omega, rho0, inv_rho0;
     double ks[2][5];       // psi-stencil coefficient of species s on the shells |c|^2 = 1,2,4,5,8
     double kx[2];          // cross coefficient (G_AB/rho0) w on |c|^2 = 1, 2

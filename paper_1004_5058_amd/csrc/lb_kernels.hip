@@ -623,6 +623,408 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
     }
 }
 
+// ------------------------------------------------------ two fused steps ---
+//
+// Steps t and t+1 in one pass over HBM.  A block of 512 threads owns a tile
+// of TW2 = 250 output columns x ly2 rows; thread j of each half of the block
+// holds column X - 3 + j (periodic).  Waves 0..3 run step t as k_step does
+// with x0 = X - 3 on rows y0-3 .. y1+2, but push the post-collision
+// populations into a four-row LDS ring instead of HBM.  Waves 4..7 run step
+// t+1 behind them: in the tick in which step t collides row a they pull row
+// a-3's populations from that ring (the shift in x of the layout becomes a
+// shift of the ring column) and stage its psi/rho, then collide row a-5;
+// they cover rows y0-2 .. y1+1 (staged) and y0 .. y1-1 (collided, columns
+// X .. X+249, stored to HBM).  Both halves meet at one LDS barrier per tick.  The step
+// t+1 pipeline runs, per row, exactly the operations of k_step on values
+// rounded to the storage format, so the pair of steps is bitwise that of two
+// k_step launches; each population crosses HBM once per two updates.
+template <class P>
+__global__ void __launch_bounds__(512)
+k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __restrict__ tiles, int ntot,
+        int src)
+{
+    constexpr int BX = 256;
+    using S = typename P::S;
+    using C = typename P::C;
+    using C2 = typename V2<C>::T;
+    static_assert(sizeof(S) == 4 || sizeof(S) == 2, "two fused steps: 4- or 2-byte storage");
+    constexpr bool DMA16 = (sizeof(S) == 2);
+    using HT = std::conditional_t<DMA16, unsigned short, unsigned>;
+    // psi and rho deviation rings of both steps, [step][slot][column index j + 2]
+    __shared__ C2 ringP[2][6][BX + 4];
+    __shared__ C2 ringR[2][6][BX + 4];
+    // step t+1's input: populations after streaming, logical row r in slot
+    // r & 3, plane q, index j + 1 (one spare entry each side for the values a
+    // wall returns to the neighbouring column)
+    __shared__ S pring[4][18][BX + 2];
+    __shared__ HT hst[4][18][DMA16 ? 12 : 4];
+    __shared__ C momx[2][BX];          // step t's wall momentum, handed to step t+1
+
+    const int tid = threadIdx.x;
+    const int role = __builtin_amdgcn_readfirstlane(tid >> 8);   // 0: step t, 1: step t+1
+    const int j = tid & (BX - 1);
+    const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) & 3), lane = tid & 63;
+    // step t's per-row halo work rotates over its four waves (rows r and r + 4
+    // share a slot of the halo ring and a wave)
+    auto halo_wave = [&](int r) { return r & 3; };
+
+    for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
+        const int L = tiles[w];
+        if (L < 0) continue;
+        const LatDesc& d = descs[L];
+        const int l = w - d.item_begin2;
+        if (l >= d.nitems2) continue;
+        int lin = l;
+        if ((d.nitems2 & 7) == 0) {
+            const int c = d.nitems2 >> 3;
+            lin = (l & 7) * c + (l >> 3);
+        }
+        const int nstrip = d.nstrip2;
+        const int strip = lin % nstrip, seg = lin / nstrip;
+        const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
+        const long long plane = d.plane;
+        const int X = strip * TW2;
+        const int y0 = seg * d.ly2;
+        const int y1 = min(y0 + d.ly2, ny);
+        auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
+        const int x0 = X - 3;
+        const unsigned xc = (unsigned)wrap(x0 + j);
+        const unsigned xp = (xc + 1 == (unsigned)nx) ? 0u : xc + 1;
+        const unsigned xm = (xc == 0) ? (unsigned)(nx - 1) : xc - 1;
+        // the columns this tile stores and whose wall momentum it counts
+        const bool own = j >= 3 && j < 3 + TW2 && X + (j - 3) < nx;
+
+        const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
+        const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
+        C ks0[5], ks1[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            ks0[k] = coef<C>(d.ks[0][k], d.fks[0][k]);
+            ks1[k] = coef<C>(d.ks[1][k], d.fks[1][k]);
+        }
+        const C kx1 = coef<C>(d.kx[0], d.fkx[0]), kx2 = coef<C>(d.kx[1], d.fkx[1]);
+        const C u_top = coef<C>(d.u_top, d.fu_top), u_bot = coef<C>(d.u_bot, d.fu_bot);
+        const C rref0 = coef<C>(d.rref[0], d.frref[0]), rref1 = coef<C>(d.rref[1], d.frref[1]);
+        const C pref0 = coef<C>(d.psiref[0], d.fpsiref[0]), pref1 = coef<C>(d.psiref[1], d.fpsiref[1]);
+        const C e0 = coef<C>(d.epsi[0], d.fepsi[0]), e1 = coef<C>(d.epsi[1], d.fepsi[1]);
+
+        const unsigned sbytes = (unsigned)(9 * plane * (long long)sizeof(S));
+        const char* fin = base + d.off_f[src];
+        const char* fout = base + d.off_f[src ^ 1];
+        const rsrc_t rin0 = make_rsrc(fin, sbytes), rin1 = make_rsrc(fin + sbytes, sbytes);
+        const rsrc_t rout0 = make_rsrc(fout, sbytes), rout1 = make_rsrc(fout + sbytes, sbytes);
+        const int es = (int)sizeof(S);
+        const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
+        const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
+        // step t's halo columns x0-2, x0-1, x0+BX, x0+BX+1 by direct-to-LDS
+        // loads, as in k_step (2-byte storage: column pairs, even nx)
+        unsigned vh = 0, vhl = 0, vhr = 0;
+        if (lane < 6) {
+            const int hc = DMA16 ? ((lane < 3) ? x0 - 4 + 2 * lane : x0 + BX - 8 + 2 * lane)
+                                 : ((lane < 2) ? x0 - 2 + lane : x0 + BX + lane - 2);
+            vh = (unsigned)wrap(hc) * es;
+            vhl = (unsigned)wrap(hc - 1) * es;
+            vhr = (unsigned)wrap(hc + 1) * es;
+        }
+        const int ndma = DMA16 ? 6 : 4;
+        double* __restrict__ stress = (double*)(base + d.off_stress);
+        const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
+        C mom_b = 0, mom_t = 0;
+
+        using R = Row<P>;
+        auto load = [&](R& fr, int r) {
+            const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+            fr.load(rin0, rin1, vm + ro, vc + ro, vp + ro, 0, pbytes);
+        };
+        auto dens = [&](const R& fr, C& da, C& db) {
+            da = fr[0];
+            db = fr[9];
+#pragma unroll
+            for (int q = 1; q < 9; ++q) { da += fr[q]; db += fr[9 + q]; }
+        };
+        auto halo_fetch = [&](int r) {
+            if (wave == halo_wave(r) && lane < ndma) {
+                const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+#pragma unroll
+                for (int q = 0; q < 18; ++q) {
+                    const int cx = CX[q % 9];
+                    const unsigned vo = ro + ((!DMA16 && cx > 0) ? vhl : ((!DMA16 && cx < 0) ? vhr : vh));
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
+                        __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
+                }
+            }
+        };
+        const int hb16 = (lane < 2) ? 2 + lane : 6 + lane;
+        auto hval = [&](int r, int q) -> C {
+            if constexpr (DMA16) {
+                return (C)__builtin_bit_cast(S, hst[r & 3][q][hb16 - CX[q % 9]]);
+            } else {
+                return (C)__builtin_bit_cast(float, hst[r & 3][q][lane]);
+            }
+        };
+        auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 8) % 6); };
+
+        // Step t: stage row r (HBM populations in fr) into ring 0, plus the
+        // four halo entries (lanes 0..3 of the row's halo wave).
+        auto stage1 = [&](const R& fr, int r) {
+            const int slot = slot6(r);
+            C da, db;
+            dens(fr, da, db);
+            ringP[0][slot][j + 2] = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
+            ringR[0][slot][j + 2] = C2{da, db};
+            if (wave == halo_wave(r) && lane < 4) {
+                // the row's own loads have completed (da, db); its halo loads
+                // were issued before them, so their data is in LDS
+                asm volatile("" ::"v"(da), "v"(db) : "memory");
+                C ha = hval(r, 0), hb = hval(r, 9);
+#pragma unroll
+                for (int q = 1; q < 9; ++q) {
+                    ha += hval(r, q);
+                    hb += hval(r, 9 + q);
+                }
+                const int hidx = (lane < 2) ? lane : BX + lane;
+                ringP[0][slot][hidx] = C2{dpsi_of(ha, e0, inv_rho0), dpsi_of(hb, e1, inv_rho0)};
+                ringR[0][slot][hidx] = C2{ha, hb};
+            }
+        };
+        // Step t+1: row r's populations from the LDS ring, pulled in x (column
+        // j - c_ix), staged into ring 1.  Beyond a wall the ghost rows are the
+        // even mirror: the bottom ones are written with their fluid rows 0 and
+        // 1 (staged later), the top ones copy their staged fluid rows.
+        auto stage2 = [&](R& fr, int r) {
+            const int slot = slot6(r);
+            if (walls && r >= ny) {
+                const int sm = slot6(2 * ny - 1 - r);
+                ringP[1][slot][j + 2] = ringP[1][sm][j + 2];
+                ringR[1][slot][j + 2] = ringR[1][sm][j + 2];
+                return;
+            }
+            if (walls && r < 0) return;
+            const int pr = r & 3;
+            if constexpr (DMA16) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    fr.v[k].x = pring[pr][2 * k][j + 1 - CX[(2 * k) % 9]];
+                    fr.v[k].y = pring[pr][2 * k + 1][j + 1 - CX[(2 * k + 1) % 9]];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 18; ++q) fr.v[q] = (C)pring[pr][q][j + 1 - CX[q % 9]];
+            }
+            C da, db;
+            dens(fr, da, db);
+            const C2 pv = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
+            const C2 rv = C2{da, db};
+            ringP[1][slot][j + 2] = pv;
+            ringR[1][slot][j + 2] = rv;
+            if (walls && r <= 1 && -1 - r >= y0 - 2) {
+                const int sg = slot6(-1 - r);
+                ringP[1][sg][j + 2] = pv;
+                ringR[1][sg][j + 2] = rv;
+            }
+        };
+
+        // Collide row y of step `k` (0: t, pushes into the LDS ring; 1: t+1,
+        // stores to HBM).  The arithmetic is k_step's.
+        auto collide = [&](const R& f, int y, int k) {
+            int sl[5];
+            sl[0] = slot6(y - 2);
+#pragma unroll
+            for (int q = 1; q < 5; ++q) sl[q] = (sl[q - 1] == 5) ? 0 : sl[q - 1] + 1;
+            C sxA = 0, syA = 0, sxB = 0, syB = 0, cxA = 0, cyA = 0, cxB = 0, cyB = 0;
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const C2 n = ringP[k][sl[dy + 2]][j + 2 + dx];
+                    const int sh = shell_of(dx, dy);
+                    if (dx != 0) {
+                        sxA += (ks0[sh] * (C)dx) * n.x;
+                        sxB += (ks1[sh] * (C)dx) * n.y;
+                    }
+                    if (dy != 0) {
+                        syA += (ks0[sh] * (C)dy) * n.x;
+                        syB += (ks1[sh] * (C)dy) * n.y;
+                    }
+                    if (sh <= 1) {
+                        const C2 m = ringR[k][sl[dy + 2]][j + 2 + dx];
+                        const C kk = (sh == 0) ? kx1 : kx2;
+                        if (dx != 0) { cxA += (kk * (C)dx) * m.y; cxB += (kk * (C)dx) * m.x; }
+                        if (dy != 0) { cyA += (kk * (C)dy) * m.y; cyB += (kk * (C)dy) * m.x; }
+                    }
+                }
+                asm volatile("" : "+v"(sxA), "+v"(syA), "+v"(sxB), "+v"(syB), "+v"(cxA), "+v"(cyA),
+                             "+v"(cxB), "+v"(cyB)::"memory");
+            }
+            const C2 p0 = ringP[k][sl[2]][j + 2];
+            const C2 r0c = ringR[k][sl[2]][j + 2];
+            const C ra = rref0 + r0c.x, rb = rref1 + r0c.y;
+            const C pa = pref0 + p0.x, pb = pref1 + p0.y;
+            const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
+            const C FxB = -pb * sxB - rb * cxB, FyB = -pb * syB - rb * cyB;
+            const C jx = (f[1] - f[3] + f[5] - f[6] - f[7] + f[8])
+                       + (f[10] - f[12] + f[14] - f[15] - f[16] + f[17]);
+            const C jy = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8])
+                       + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
+            const C inv_rho = rcp(ra + rb);
+            const C ux = jx * inv_rho, uy = jy * inv_rho;
+            const int yw = (y < 0) ? y + ny : (y >= ny ? y - ny : y);   // periodic image of a step-t row
+            const C gx = (body != nullptr) ? (C)body[yw] * inv_rho : (C)0;
+            const bool bot = walls && (y == 0);
+            const bool top = walls && (y == ny - 1);
+            const bool count = own && y >= y0 && y < y1;   // wall momentum owned by this tile
+            const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+            const unsigned vrow_m = (unsigned)(ym * rbytes), vrow_0 = (unsigned)(y * rbytes),
+                           vrow_p = (unsigned)(yp * rbytes);
+            auto relax_push = [&](int s, C rs, C drs, C Fx, C Fy) {
+                const C inv = rcp(rs);
+                const C vx = ux + tau * (Fx * inv + gx);
+                const C vy = uy + tau * Fy * inv;
+                const C usq = (C)1.5 * (vx * vx + vy * vy);
+                const C r0 = rs * (C)(4.0 / 9.0), r1 = rs * (C)(1.0 / 9.0), r2 = rs * (C)(1.0 / 36.0);
+                const C d1 = drs * (C)(1.0 / 9.0), d2 = drs * (C)(1.0 / 36.0);
+                const int o = 9 * s;
+                C fs[9];
+                fs[0] = f[o + 0] - omega * (f[o + 0] - (drs * (C)(4.0 / 9.0) - r0 * usq));
+                auto pair = [&](int ip, int im, C rw, C dw, C cu) {
+                    const C sym = dw + rw * ((C)4.5 * cu * cu - usq);
+                    const C anti = rw * ((C)3 * cu);
+                    fs[ip] = f[o + ip] - omega * (f[o + ip] - (sym + anti));
+                    fs[im] = f[o + im] - omega * (f[o + im] - (sym - anti));
+                };
+                pair(1, 3, r1, d1, vx);
+                pair(2, 4, r1, d1, vy);
+                pair(5, 7, r2, d2, vx + vy);
+                pair(6, 8, r2, d2, vy - vx);
+                if (k == 0) {
+                    // into the ring: row y + c_iy at the lane's own index; a
+                    // population leaving through a wall returns as OPP[i] at
+                    // index j + c_ix of row y (the layout's shift, as in HBM)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const int cx = CX[i], cy = CY[i];
+                        if (cy < 0 && bot) {
+                            const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
+                            pring[y & 3][o + OPP[i]][j + 1 + cx] = (S)back;
+                            if (cx != 0 && count) mom_b += (C)cx * (fs[i] + back);
+                        } else if (cy > 0 && top) {
+                            const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
+                            pring[y & 3][o + OPP[i]][j + 1 + cx] = (S)back;
+                            if (cx != 0 && count) mom_t += (C)cx * (fs[i] + back);
+                        } else {
+                            pring[(y + cy) & 3][o + i][j + 1] = (S)fs[i];
+                        }
+                    }
+                    return;
+                }
+                if (!own) return;
+                const rsrc_t ro = (s == 0) ? rout0 : rout1;
+                if (!(bot || top)) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const int cy = CY[i];
+                        const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
+                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
+                    }
+                    return;
+                }
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int cx = CX[i], cy = CY[i];
+                    const unsigned vback = (cx == 0) ? vc : (cx > 0 ? vp : vm);
+                    if (cy < 0 && bot) {
+                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
+                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
+                        if (cx != 0) mom_b += (C)cx * (fs[i] + back);
+                    } else if (cy > 0 && top) {
+                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
+                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
+                        if (cx != 0) mom_t += (C)cx * (fs[i] + back);
+                    } else {
+                        const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
+                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
+                    }
+                }
+            };
+            relax_push(0, ra, r0c.x, FxA, FyA);
+            relax_push(1, rb, r0c.y, FxB, FyB);
+        };
+
+        // Step t collides rows A0 .. A1-1; tick a stages row a+2 and collides
+        // row a of step t, and stages row a-3 and collides row a-5 of step
+        // t+1, each half around the same barrier.  Step t's prologue stages rows A0-2 .. A0+1 and has rows
+        // A0 .. A0+2 loaded, as k_step's; its loads run up to row A1+1.
+        const int A0 = y0 - 3, A1 = y1 + 3, T1 = y1 + 4;
+        R F0, F1, F2, F3;
+        if (role == 0) {
+            halo_fetch(A0 - 2);
+            load(F2, A0 - 2);
+            halo_fetch(A0 - 1);
+            load(F3, A0 - 1);
+            stage1(F2, A0 - 2);
+            stage1(F3, A0 - 1);
+            halo_fetch(A0);
+            load(F0, A0);
+            halo_fetch(A0 + 1);
+            load(F1, A0 + 1);
+            halo_fetch(A0 + 2);
+            load(F2, A0 + 2);
+            stage1(F0, A0);
+            stage1(F1, A0 + 1);
+        }
+        auto tick = [&](int a, R& fc, R& fs2, R& fl) {
+            if (role == 0) {
+                if (a < A1) {
+                    stage1(fs2, a + 2);
+                    if (a + 3 <= A1 + 1) {
+                        halo_fetch(a + 3);
+                        load(fl, a + 3);
+                    }
+                }
+            } else {
+                // row a-3 is complete since tick a-2 and visible since the
+                // previous barrier; staging it before this tick's barrier
+                // balances the two halves (each: stage, barrier, collide)
+                const int r = a - 3;
+                if (r >= y0 - 2 && r <= y1 + 1) stage2(fs2, r);
+            }
+            lds_barrier();
+            if (role == 0) {
+                if (a < A1 && (!walls || (a >= 0 && a < ny))) collide(fc, a, 0);
+            } else {
+                const int c = a - 5;
+                if (c >= y0 && c < y1) collide(fc, c, 1);
+            }
+        };
+        for (int a = A0; a <= T1; a += 4) {
+            tick(a, F0, F2, F3);
+            if (a + 1 <= T1) tick(a + 1, F1, F3, F0);
+            if (a + 2 <= T1) tick(a + 2, F2, F0, F1);
+            if (a + 3 <= T1) tick(a + 3, F3, F1, F2);
+        }
+        // wall momentum in FP64, step t's first, then step t+1's (the order
+        // of two single steps)
+        if (role == 0) {
+            momx[0][j] = mom_b;
+            momx[1][j] = mom_t;
+        }
+        __syncthreads();
+        if (role == 1 && own && walls) {
+            if (y0 == 0) {
+                stress[xc] += (double)momx[0][j];
+                stress[xc] += (double)mom_b;
+            }
+            if (y1 == ny) {
+                stress[nx + xc] += (double)momx[1][j];
+                stress[nx + xc] += (double)mom_t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------- auxiliary ---
 
 template <class P>
@@ -1475,6 +1877,28 @@ size_t step_lds_bytes(int storage, int bx, int ly)
     case 5 * 1000 + 64: return lds_of(k_step_mom<64, MomF64>, mom_dyn_lds<MomF64::C>(64, ly));
     case 5 * 1000 + 128: return lds_of(k_step_mom<128, MomF64>, mom_dyn_lds<MomF64::C>(128, ly));
     case 5 * 1000 + 256: return lds_of(k_step_mom<256, MomF64>, mom_dyn_lds<MomF64::C>(256, ly));
+    default: return 0;
+    }
+}
+
+hipError_t launch_step2(int storage, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
+                        int grid, hipStream_t s)
+{
+    switch (storage) {
+    case 1: hipLaunchKernelGGL((k_step2<StF32>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src); break;
+    case 2: hipLaunchKernelGGL((k_step2<StF16>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src); break;
+    case 3: hipLaunchKernelGGL((k_step2<StBF16>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+size_t step2_lds_bytes(int storage)
+{
+    switch (storage) {
+    case 1: return lds_of(k_step2<StF32>, 0);
+    case 2: return lds_of(k_step2<StF16>, 0);
+    case 3: return lds_of(k_step2<StBF16>, 0);
     default: return 0;
     }
 }

@@ -12,6 +12,12 @@ namespace lbk {
 // reads the local equilibria in place instead of pulling from neighbours).
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int first, int grid, int ly, hipStream_t s);
+// Steps t and t+1 in one launch (k_step2, 512 threads, tiles of TW2 columns):
+// reads buffer src, writes buffer src ^ 1.  Storage 1..3 only.
+constexpr int TW2 = 250;
+hipError_t launch_step2(int storage, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
+                        int grid, hipStream_t s);
+size_t step2_lds_bytes(int storage);
 // Shared memory (bytes) one step block needs for tile width bx and ly rows;
 // 0 if the storage has no step kernel of that width.
 size_t step_lds_bytes(int storage, int bx, int ly);

@@ -66,6 +66,8 @@ def load_library(path=LIB_PATH):
         "lb_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
         "lb_init": [P, _VP, ctypes.c_size_t, _VP, _DP, _DP, _DP, _DP, ctypes.POINTER(H)],
         "lb_step": [H, ctypes.c_int32],
+        "lb_set_fusion": [H, ctypes.c_int32, ctypes.c_int32],
+        "lbb_set_fusion": [H, ctypes.c_int32, ctypes.c_int32],
         "lb_fields": [H, _DP, _DP, _DP, _DP],
         "lb_fields_device": [H, _VP, _VP, _VP, _VP],
         "lb_populations": [H, _DP],
@@ -295,6 +297,10 @@ class Lattice:
     def set_graph(self, steps_per_graph):
         _check(_lib.lb_set_graph(self._h, int(steps_per_graph)))
 
+    def set_fusion(self, steps_per_pass, ly2=0):
+        """1 or 2 time steps per pass of the step kernel (2: FP32/16-bit storage, no profile)."""
+        _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
+
     def autotune(self, cache_path=None, steps=20):
         """Pick the fastest launch shape (state preserved); returns (bx, ly, ms)."""
         bx, ly, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
@@ -411,6 +417,10 @@ class Batch:
 
     def set_graph(self, steps_per_graph):
         _check(_lib.lbb_set_graph(self._h, int(steps_per_graph)))
+
+    def set_fusion(self, steps_per_pass, ly2=0):
+        """1 or 2 time steps per pass of the step kernel (2: FP32/16-bit storage, no profile)."""
+        _check(_lib.lbb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def time_steps(self, n):
         ms = ctypes.c_double()

@@ -1,0 +1,113 @@
+"""Two time steps per pass (lb_set_fusion, FP32 storage): the fused kernel
+keeps step t's populations in on-chip memory and runs step t+1 behind it.  It
+performs the operations of two single steps on the same values (the library is
+built with multiply-add contraction inside expressions only), so populations,
+wall stresses and step counts must equal the single-step path bit for bit, with
+walls or periodic y, body force, any tile height, odd step counts (the last
+step runs alone) and graphs of either parity."""
+import numpy as np
+import pytest
+
+from gpu_common import compare_fields, gpu_lattice, need_gpu, oracle_params, oracle_run
+from paper_1004_5058_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsion"):
+    u = 0.02 if walls else 0.0
+    ra, rb = (inputs.emulsion(nx, ny, seed=seed) if init == "emulsion" else inputs.noise(nx, ny, seed))
+    ux, uy = inputs.couette(nx, ny, u, -u) if walls else (None, None)
+    kw = dict(fx_amp=3e-5, fx_k=0.21) if body else {}
+    out = []
+    for fused in (False, True):
+        lat = gpu_lattice(nx, ny, ra, rb, ux, uy, walls=walls, u_top=u, u_bot=-u, storage=storage, **kw)
+        lat.set_graph(graph)
+        if fused:
+            lat.set_fusion(2, ly2)
+        lat.step(steps)
+        out.append((lat.populations(), lat.stress(), lat.time()))
+        lat.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32"])
+@pytest.mark.parametrize("nx,ny,walls,body,ly2", [(600, 300, True, False, 0), (500, 120, False, True, 7),
+                                                   (252, 31, True, True, 1), (8, 6, True, False, 64),
+                                                   (1000, 40, False, False, 0), (6, 2, False, False, 0)])
+def test_fused_bitwise_equals_single_steps(storage, nx, ny, walls, body, ly2):
+    (p1, s1, t1), (p2, s2, t2) = _pair(nx, ny, storage, walls, body, 30, ly2, 32)
+    assert t1 == t2 == 30
+    np.testing.assert_array_equal(p2, p1)
+    assert s2 == s1
+
+
+@pytest.mark.parametrize("steps,graph", [(31, 0), (31, 6), (40, 6), (37, 32)])
+def test_fused_odd_steps_and_graph_parity(steps, graph):
+    """Odd step counts end with one single step; graphs of 6 steps hold three
+    fused pairs (an odd number of buffer swaps per replay)."""
+    (p1, s1, t1), (p2, s2, t2) = _pair(333, 97, "f32", True, True, steps, 0, graph)
+    assert t1 == t2 == steps
+    np.testing.assert_array_equal(p2, p1)
+    assert s2 == s1
+
+
+def test_fused_odd_width_fp32():
+    (p1, s1, _), (p2, s2, _) = _pair(257, 64, "f32", True, False, 20, 16, 32)
+    np.testing.assert_array_equal(p2, p1)
+    assert s2 == s1
+
+
+def test_fused_matches_oracle():
+    nx, ny, u, steps = 300, 128, 0.01, 100
+    ra, rb = inputs.noise(nx, ny, 0)
+    p = oracle_params(nx, ny, True, u, -u)
+    g, sb, st = oracle_run(p, ra, rb, None, None, steps)
+    lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32")
+    lat.set_fusion(2)
+    lat.step(steps)
+    e = compare_fields(lat, p, g, 1e-6)
+    gb, gt, n = lat.stress()
+    assert n == steps
+    assert abs(gb - sb) / abs(sb) < 1e-5 and abs(gt - st) / abs(st) < 1e-5
+    print(f"\nfused FP32 {nx}x{ny}, {steps} steps: {e}")
+
+
+def test_fused_batch_equals_single_steps():
+    from paper_1004_5058_amd import lb
+    specs = []
+    for k, (nx, ny, walls) in enumerate([(512, 256, True), (300, 77, False), (1024, 130, True), (40, 9, True)]):
+        ra, rb = inputs.emulsion(nx, ny, seed=20 + k)
+        u = 0.01 * (k + 1) if walls else 0.0
+        specs.append(dict(nx=nx, ny=ny, rho_a=ra, rho_b=rb, ux=None, uy=None, walls=walls, u_top=u, u_bot=-u,
+                          g_aa2=7.8 + 0.1 * k))
+    res = []
+    for fused in (False, True):
+        b = lb.Batch(specs, storage="f32", profile=False)
+        if fused:
+            b.set_fusion(2)
+        b.step(24)
+        res.append(([b.fields(k) for k in range(len(specs))], b.stress()))
+        b.close()
+    for a, c in zip(res[0][0], res[1][0]):
+        for x, y in zip(a, c):
+            np.testing.assert_array_equal(y, x)
+    for x, y in zip(res[0][1][:2], res[1][1][:2]):
+        np.testing.assert_array_equal(y, x)
+    assert res[0][1][2] == res[1][1][2] == 24
+
+
+def test_fused_refused_where_not_built():
+    from paper_1004_5058_amd import lb
+    ra, rb = inputs.noise(64, 16, 1)
+    for storage, kw in (("f64", {}), ("mom32", {}), ("f16dev", {}), ("bf16dev", {}), ("f32", dict(profile=True))):
+        lat = gpu_lattice(64, 16, ra, rb, storage=storage, **kw)
+        with pytest.raises(lb.LBError, match="two steps per pass"):
+            lat.set_fusion(2)
+        lat.step(2)           # still steps, one step per pass
+        lat.close()

@@ -71,7 +71,10 @@ def test_newtonian_kolmogorov_flow_on_gpu():
     g, _, _ = oracle_run(p, ra, ra.copy(), None, None, steps)
     _, _, oux, _ = O.fields(p, g)
     R_ref = K.response(oux.mean(axis=1), U0)
-    for storage, tol in (("f64", 1e-12), ("f32", 3e-5)):
+    # FP32 bound: storage rounding (~3e-8 per population and step) walks over
+    # the relaxation time 1/(nu k^2) ~ 625 steps of this flow, ~sqrt(625) x
+    # 3e-8 ~ 7.5e-7 in u, i.e. ~7.5e-5 in R at U0 = 0.01: bound 1e-4.
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-4)):
         lat = gpu_lattice(nx, L, ra, ra.copy(), walls=False, storage=storage, profile=True, tau=tau,
                           fx_amp=F0, fx_k=kf, **ZERO)
         lat.step(steps)
