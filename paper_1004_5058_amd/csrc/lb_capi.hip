@@ -732,8 +732,7 @@ lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
 }
 
 // Two time steps per pass (k_step2): FP32 population storage, no profile
-// accumulators.  ly2 = 0 picks the tile height.  (The kernel is also built for
-// 16-bit storage, where it measured slower than single steps.)
+// accumulators.  ly2 = 0 picks the tile height.
 lb_status set_fusion(lbb_handle* h, int k, int ly2)
 {
     if (k != 1 && k != 2) return fail(LB_EINVAL, "steps per pass must be 1 or 2");

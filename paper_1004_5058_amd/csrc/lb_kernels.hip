@@ -647,9 +647,10 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     using S = typename P::S;
     using C = typename P::C;
     using C2 = typename V2<C>::T;
-    static_assert(sizeof(S) == 4 || sizeof(S) == 2, "two fused steps: 4- or 2-byte storage");
-    constexpr bool DMA16 = (sizeof(S) == 2);
-    using HT = std::conditional_t<DMA16, unsigned short, unsigned>;
+    // 4-byte storage only: the halo of step t is one dword per column and
+    // plane; the paired 2-byte window would start at the odd column X - 7
+    static_assert(sizeof(S) == 4, "two fused steps: 4-byte storage");
+    using HT = unsigned;
     // psi and rho deviation rings of both steps, [step][slot][column index j + 2]
     __shared__ C2 ringP[2][6][BX + 4];
     __shared__ C2 ringR[2][6][BX + 4];
@@ -657,7 +658,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     // r & 3, plane q, index j + 1 (one spare entry each side for the values a
     // wall returns to the neighbouring column)
     __shared__ S pring[4][18][BX + 2];
-    __shared__ HT hst[4][18][DMA16 ? 12 : 4];
+    __shared__ HT hst[4][18][4];
     __shared__ C momx[2][BX];          // step t's wall momentum, handed to step t+1
 
     const int tid = threadIdx.x;
@@ -717,16 +718,15 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
         const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
         // step t's halo columns x0-2, x0-1, x0+BX, x0+BX+1 by direct-to-LDS
-        // loads, as in k_step (2-byte storage: column pairs, even nx)
+        // loads, as in k_step
         unsigned vh = 0, vhl = 0, vhr = 0;
-        if (lane < 6) {
-            const int hc = DMA16 ? ((lane < 3) ? x0 - 4 + 2 * lane : x0 + BX - 8 + 2 * lane)
-                                 : ((lane < 2) ? x0 - 2 + lane : x0 + BX + lane - 2);
+        if (lane < 4) {
+            const int hc = (lane < 2) ? x0 - 2 + lane : x0 + BX + lane - 2;
             vh = (unsigned)wrap(hc) * es;
             vhl = (unsigned)wrap(hc - 1) * es;
             vhr = (unsigned)wrap(hc + 1) * es;
         }
-        const int ndma = DMA16 ? 6 : 4;
+        const int ndma = 4;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
         C mom_b = 0, mom_t = 0;
@@ -748,21 +748,14 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
 #pragma unroll
                 for (int q = 0; q < 18; ++q) {
                     const int cx = CX[q % 9];
-                    const unsigned vo = ro + ((!DMA16 && cx > 0) ? vhl : ((!DMA16 && cx < 0) ? vhr : vh));
+                    const unsigned vo = ro + (cx > 0 ? vhl : (cx < 0 ? vhr : vh));
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
                         q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
                         __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
                 }
             }
         };
-        const int hb16 = (lane < 2) ? 2 + lane : 6 + lane;
-        auto hval = [&](int r, int q) -> C {
-            if constexpr (DMA16) {
-                return (C)__builtin_bit_cast(S, hst[r & 3][q][hb16 - CX[q % 9]]);
-            } else {
-                return (C)__builtin_bit_cast(float, hst[r & 3][q][lane]);
-            }
-        };
+        auto hval = [&](int r, int q) -> C { return (C)__builtin_bit_cast(float, hst[r & 3][q][lane]); };
         auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 8) % 6); };
 
         // Step t: stage row r (HBM populations in fr) into ring 0, plus the
@@ -802,16 +795,8 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             }
             if (walls && r < 0) return;
             const int pr = r & 3;
-            if constexpr (DMA16) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    fr.v[k].x = pring[pr][2 * k][j + 1 - CX[(2 * k) % 9]];
-                    fr.v[k].y = pring[pr][2 * k + 1][j + 1 - CX[(2 * k + 1) % 9]];
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 18; ++q) fr.v[q] = (C)pring[pr][q][j + 1 - CX[q % 9]];
-            }
+            for (int q = 0; q < 18; ++q) fr.v[q] = (C)pring[pr][q][j + 1 - CX[q % 9]];
             C da, db;
             dens(fr, da, db);
             const C2 pv = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
@@ -1884,23 +1869,14 @@ size_t step_lds_bytes(int storage, int bx, int ly)
 hipError_t launch_step2(int storage, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
                         int grid, hipStream_t s)
 {
-    switch (storage) {
-    case 1: hipLaunchKernelGGL((k_step2<StF32>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src); break;
-    case 2: hipLaunchKernelGGL((k_step2<StF16>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src); break;
-    case 3: hipLaunchKernelGGL((k_step2<StBF16>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (storage != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_step2<StF32>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src);
     return hipGetLastError();
 }
 
 size_t step2_lds_bytes(int storage)
 {
-    switch (storage) {
-    case 1: return lds_of(k_step2<StF32>, 0);
-    case 2: return lds_of(k_step2<StF16>, 0);
-    case 3: return lds_of(k_step2<StBF16>, 0);
-    default: return 0;
-    }
+    return storage == 1 ? lds_of(k_step2<StF32>, 0) : 0;
 }
 
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,

@@ -13,7 +13,7 @@ namespace lbk {
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int first, int grid, int ly, hipStream_t s);
 // Steps t and t+1 in one launch (k_step2, 512 threads, tiles of TW2 columns):
-// reads buffer src, writes buffer src ^ 1.  Storage 1..3 only.
+// reads buffer src, writes buffer src ^ 1.  FP32 storage (code 1) only.
 constexpr int TW2 = 250;
 hipError_t launch_step2(int storage, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
                         int grid, hipStream_t s);
