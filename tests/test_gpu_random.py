@@ -45,22 +45,28 @@ def _draw(seed):
         kw["tau"] = 1.0          # the moment form holds the state at tau = 1 only
     bx = int(r.choice([64, 128, 256] + ([512] if storage in ("f32", "f16dev", "bf16dev") else [])))
     ly = int(r.integers(1, 200))
-    return nx, ny, walls, u_top, u_bot, kw, storage, bx, ly
+    # FP32: two steps per pass in about half of the cases, random fused tile height
+    fuse = storage == "f32" and bool(r.integers(2))
+    ly2 = int(r.integers(0, 100))
+    return nx, ny, walls, u_top, u_bot, kw, storage, bx, ly, fuse, ly2
 
 
 @pytest.mark.parametrize("seed", range(36))
 def test_random_configuration_matches_oracle(seed):
-    nx, ny, walls, u_top, u_bot, kw, storage, bx, ly = _draw(seed)
+    nx, ny, walls, u_top, u_bot, kw, storage, bx, ly, fuse, ly2 = _draw(seed)
     ra, rb = inputs.noise(nx, ny, seed)
     p = oracle_params(nx, ny, walls, u_top, u_bot, **kw)
     g, _, _ = oracle_run(p, ra, rb, None, None, 30)
     lat = gpu_lattice(nx, ny, ra, rb, walls=walls, u_top=u_top, u_bot=u_bot, storage=storage, **kw)
     lat.set_launch(bx, ly)
+    if fuse:
+        lat.set_fusion(2, ly2)
     lat.step(30)
     tol = TOL[storage]
     e = compare_fields(lat, p, g, tol)
     ep = err_pop(lat.populations(), g)
-    print(f"\nseed {seed}: {nx}x{ny} walls={walls} {storage} shape {bx}x{ly} tau {kw['tau']:.3f}: "
+    print(f"\nseed {seed}: {nx}x{ny} walls={walls} {storage}{' fused ly2 %d' % ly2 if fuse else ''} "
+          f"shape {bx}x{ly} tau {kw['tau']:.3f}: "
           f"{max(e.values()):.2e}, populations {ep:.2e}")
     assert ep <= 10 * tol
     lat.close()
@@ -106,9 +112,12 @@ def test_random_batch_matches_oracle(seed):
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     grid = int(r.choice([0, ncu, 2 * ncu]))
     graph = int(r.choice([0, 2, 8, 32]))
+    fuse = storage == "f32" and bool(r.integers(2))
     b = lb.Batch(specs, storage=storage, profile=False)
     b.set_launch(bx, ly, grid)
     b.set_graph(graph)
+    if fuse:
+        b.set_fusion(2, int(r.integers(0, 60)))
     b.step(30)
     worst = 0.0
     for k, (p, ra, rb) in enumerate(cases):
@@ -116,5 +125,6 @@ def test_random_batch_matches_oracle(seed):
         e = compare_fields(_Member(b, k), p, g, TOL[storage])
         worst = max(worst, max(e.values()))
     b.close()
-    print(f"\nbatch seed {seed}: {len(specs)} lattices {storage} shape {bx}x{ly} grid {grid} graph {graph}: "
+    print(f"\nbatch seed {seed}: {len(specs)} lattices {storage}{' fused' if fuse else ''} shape {bx}x{ly} "
+          f"grid {grid} graph {graph}: "
           f"worst {worst:.2e}")
