@@ -92,8 +92,9 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
                      **inputs.COUPLINGS)
     del ra, rb, ux, uy
     shape = lat.autotune(tune_cache, steps=10) if tune_cache is not None else None
-    if STEPS_PER_LAUNCH.get(variant, 1) == 2:
-        lat.set_fusion(2)
+    if variant_storage(variant) == "f32":
+        # the tuner may pick either; each variant states its own steps per pass
+        lat.set_fusion(STEPS_PER_LAUNCH.get(variant, 1))
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -194,12 +194,16 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
 /* Autotuner: times `steps` steps of every candidate launch shape (bx in
  * {64, 128, 256, 512} as lb_set_launch admits them, ly in {8..256}, shapes
  * within the device's shared memory per block; for batches also persistent grids of 1, 2
- * and 4 blocks per compute unit) on this lattice, applies the fastest and
- * restores the simulation state exactly (populations, accumulators, step
- * count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid, ms}},
- * key "<gfx arch>/<storage>/<nx>x<ny>" (batches: "batch<n>_<sites>"); a cached
- * entry is applied without timing, a new result is added.  Synchronises.
- * Allocates a temporary device copy of the state while timing. */
+ * and 4 blocks per compute unit) on this lattice; where lb_set_fusion admits
+ * two steps per pass (FP32, no profile), also that mode behind the best
+ * shape.  Applies the fastest (shape and steps per pass; *ms is its time per
+ * step) and restores the simulation state exactly (populations, accumulators,
+ * step count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid,
+ * fusion, ly2, ms}}, key "<gfx arch>/<storage>/<nx>x<ny>" (batches:
+ * "batch<n>_<sites>"); a cached entry is applied without timing (its fusion
+ * only where admitted; entries without it mean one step per pass), a new
+ * result is added.  Synchronises.  Allocates a temporary device copy of the
+ * state while timing. */
 lb_status lb_autotune(lb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
                       double* ms);
 lb_status lbb_autotune(lbb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,

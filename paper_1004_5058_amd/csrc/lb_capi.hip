@@ -793,8 +793,18 @@ lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
 
 struct TuneEntry {
     int bx = 0, ly = 0, grid = 0;
+    int fusion = 1, ly2 = 0;   // time steps per pass and fused tile height (0: automatic)
     double ms = 0;
 };
+
+// Whether the handle may run two steps per pass (set_fusion's conditions).
+bool fusion_allowed(const lbb_handle* h)
+{
+    if (h->storage != LB_F32) return false;
+    for (const Lat& a : h->lats)
+        if (a.p.profile) return false;
+    return true;
+}
 
 std::string arch_name()
 {
@@ -844,6 +854,8 @@ std::vector<std::pair<std::string, TuneEntry>> read_cache(const char* path)
         if ((p = strstr(q2, "\"ly\":"))) e.ly = atoi(p + 5);
         if ((p = strstr(q2, "\"grid\":"))) e.grid = atoi(p + 7);
         if ((p = strstr(q2, "\"ms\":"))) e.ms = strtod(p + 5, nullptr);
+        if ((p = strstr(q2, "\"fusion\":"))) e.fusion = atoi(p + 9);
+        if ((p = strstr(q2, "\"ly2\":"))) e.ly2 = atoi(p + 6);
         out.emplace_back(std::string(q1 + 1, q2 - q1 - 1), e);
     }
     fclose(f);
@@ -857,9 +869,9 @@ lb_status write_cache(const char* path, const std::vector<std::pair<std::string,
     if (!f) return fail(LB_EINVAL, "cannot write tuning cache %s", path);
     fprintf(f, "{\n");
     for (size_t i = 0; i < ents.size(); ++i)
-        fprintf(f, "\"%s\": {\"bx\": %d, \"ly\": %d, \"grid\": %d, \"ms\": %.6f}%s\n", ents[i].first.c_str(),
-                ents[i].second.bx, ents[i].second.ly, ents[i].second.grid, ents[i].second.ms,
-                i + 1 < ents.size() ? "," : "");
+        fprintf(f, "\"%s\": {\"bx\": %d, \"ly\": %d, \"grid\": %d, \"fusion\": %d, \"ly2\": %d, \"ms\": %.6f}%s\n",
+                ents[i].first.c_str(), ents[i].second.bx, ents[i].second.ly, ents[i].second.grid,
+                ents[i].second.fusion, ents[i].second.ly2, ents[i].second.ms, i + 1 < ents.size() ? "," : "");
     fprintf(f, "}\n");
     fclose(f);
     if (rename(tmp.c_str(), path) != 0) return fail(LB_EINVAL, "cannot replace tuning cache %s", path);
@@ -874,6 +886,9 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     for (auto& kv : cache)
         if (kv.first == key && kv.second.bx) {
             lb_status st = set_launch(h, kv.second.bx, kv.second.ly, kv.second.grid);
+            if (st != LB_OK) return st;
+            const bool fuse = kv.second.fusion == 2 && fusion_allowed(h);
+            st = set_fusion(h, fuse ? 2 : 1, fuse ? kv.second.ly2 : 0);
             if (st != LB_OK) return st;
             if (best_out) *best_out = kv.second;
             return LB_OK;
@@ -899,7 +914,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     const int cur = h->cur;
     const int64_t t = h->t, ns = h->nsamples;
     const int bx0 = h->bx, ly0 = h->ly, grid0 = h->grid, gs0 = h->graph_steps, wd0 = h->watchdog;
-    const int fu0 = h->fusion;
+    const int fu0 = h->fusion, ly20 = h->ly2;
     h->graph_steps = 0;
     h->watchdog = 0;
     h->fusion = 1;          // the single-step kernel's shapes are what is tuned
@@ -934,6 +949,17 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
         }
         if (st != LB_OK) break;
     }
+    // two steps per pass, automatic tile height, behind the best single-step
+    // shape (which any odd remaining step uses)
+    if (st == LB_OK && best.bx && fusion_allowed(h)) {
+        st = set_launch(h, best.bx, best.ly, best.grid);
+        if (st == LB_OK) st = set_fusion(h, 2, 0);
+        if (st == LB_OK) st = steps_direct_warm(h, 2);
+        double ms = 0;
+        if (st == LB_OK) st = time_steps(h, steps + (steps & 1), &ms);
+        if (st == LB_OK && ms < best.ms) { best.fusion = 2; best.ly2 = 0; best.ms = ms; }
+        h->fusion = 1;
+    }
     // restore the state
     o = 0;
     h->cur = cur;
@@ -949,12 +975,15 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     h->nsamples = ns;
     h->graph_steps = gs0;
     h->fusion = fu0;
+    h->ly2 = ly20;
     h->watchdog = wd0;
     if (st != LB_OK) {
         (void)set_launch(h, bx0, ly0, grid0);
         return st;
     }
     st = set_launch(h, best.bx, best.ly, best.grid);
+    if (st != LB_OK) return st;
+    st = set_fusion(h, best.fusion, best.ly2);
     if (st != LB_OK) return st;
     if (best_out) *best_out = best;
     if (cache_path) {

@@ -302,7 +302,8 @@ class Lattice:
         _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def autotune(self, cache_path=None, steps=20):
-        """Pick the fastest launch shape (state preserved); returns (bx, ly, ms)."""
+        """Pick the fastest launch shape, and for FP32 without profile the steps per
+        pass (state preserved); returns (bx, ly, ms per step)."""
         bx, ly, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         path = cache_path.encode() if cache_path else None
         _check(_lib.lb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(ms)))
@@ -428,7 +429,8 @@ class Batch:
         return ms.value
 
     def autotune(self, cache_path=None, steps=10):
-        """Pick the fastest launch shape and grid (state preserved); returns (bx, ly, grid, ms)."""
+        """Pick the fastest launch shape and grid, and for FP32 without profile the
+        steps per pass (state preserved); returns (bx, ly, grid, ms per step)."""
         bx, ly, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         path = cache_path.encode() if cache_path else None
         _check(_lib.lbb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(grid),

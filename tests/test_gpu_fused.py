@@ -111,3 +111,30 @@ def test_fused_refused_where_not_built():
             lat.set_fusion(2)
         lat.step(2)           # still steps, one step per pass
         lat.close()
+
+
+def test_autotune_considers_two_steps_per_pass(tmp_path):
+    """The tuner also times two steps per pass for an FP32 lattice without
+    profile, applies the faster mode, preserves the state (either mode is
+    bitwise the single-step result) and records the choice in the cache; a
+    profile-enabled lattice of the same key runs one step per pass."""
+    import json
+    nx, ny, u = 1024, 512, 0.02
+    ra, rb = inputs.emulsion(nx, ny, seed=3)
+    ref = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32")
+    ref.step(10)
+    lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32")
+    lat.step(4)
+    cache = str(tmp_path / "tune.json")
+    bx, ly, ms = lat.autotune(cache, steps=4)
+    assert lat.time() == 4 and ms > 0
+    lat.step(6)
+    np.testing.assert_array_equal(lat.populations(), ref.populations())
+    assert lat.stress() == ref.stress()
+    (key, ent), = json.load(open(cache)).items()
+    assert ent["fusion"] in (1, 2) and "ly2" in ent and (ent["bx"], ent["ly"]) == (bx, ly)
+    print(f"\n{key}: {ent}")
+    prof = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32", profile=True)
+    assert prof.autotune(cache, steps=4)[:2] == (bx, ly)
+    prof.step(4)
+    assert prof.time() == 4 and prof.profile()[1] == 4
