@@ -837,7 +837,8 @@ std::string tune_key(const lbb_handle* h)
     return buf;
 }
 
-// Reads {"key": {"bx": .., "ly": .., "grid": .., "ms": ..}, ...} one entry per line.
+// Reads {"key": {"bx": .., "ly": .., "grid": .., "fusion": .., "ly2": .., "ms": ..}, ...}
+// one entry per line; an entry without "fusion" runs one step per pass.
 std::vector<std::pair<std::string, TuneEntry>> read_cache(const char* path)
 {
     std::vector<std::pair<std::string, TuneEntry>> out;

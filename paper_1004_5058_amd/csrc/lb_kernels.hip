@@ -939,8 +939,12 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
 
         // Step t collides rows A0 .. A1-1; tick a stages row a+2 and collides
         // row a of step t, and stages row a-3 and collides row a-5 of step
-        // t+1, each half around the same barrier.  Step t's prologue stages rows A0-2 .. A0+1 and has rows
-        // A0 .. A0+2 loaded, as k_step's; its loads run up to row A1+1.
+        // t+1, each half around the same barrier.  The two halves run loops
+        // of their own over the same ticks A0 .. T1 with exactly one barrier
+        // per tick (the counts match by construction), each with its own
+        // rotating register rows.  Step t's prologue stages rows A0-2 .. A0+1
+        // and has rows A0 .. A0+2 loaded, as k_step's; its loads run up to
+        // row A1+1.
         const int A0 = y0 - 3, A1 = y1 + 3, T1 = y1 + 4;
         R F0, F1, F2, F3;
         if (role == 0) {
@@ -958,9 +962,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             load(F2, A0 + 2);
             stage1(F0, A0);
             stage1(F1, A0 + 1);
-        }
-        auto tick = [&](int a, R& fc, R& fs2, R& fl) {
-            if (role == 0) {
+            auto tick = [&](int a, const R& fc, const R& fs2, R& fl) {
                 if (a < A1) {
                     stage1(fs2, a + 2);
                     if (a + 3 <= A1 + 1) {
@@ -968,26 +970,33 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                         load(fl, a + 3);
                     }
                 }
-            } else {
-                // row a-3 is complete since tick a-2 and visible since the
-                // previous barrier; staging it before this tick's barrier
-                // balances the two halves (each: stage, barrier, collide)
+                lds_barrier();
+                if (a < A1 && (!walls || (a >= 0 && a < ny))) collide(fc, a, 0);
+            };
+            for (int a = A0; a <= T1; a += 4) {
+                tick(a, F0, F2, F3);
+                if (a + 1 <= T1) tick(a + 1, F1, F3, F0);
+                if (a + 2 <= T1) tick(a + 2, F2, F0, F1);
+                if (a + 3 <= T1) tick(a + 3, F3, F1, F2);
+            }
+        } else {
+            // row a-3 is complete since tick a-2 and visible since the
+            // previous barrier; staging it before this tick's barrier
+            // balances the two halves (each: stage, barrier, collide).  The
+            // row staged in tick a is collided in tick a+2.
+            auto tick = [&](int a, const R& fc, R& fs2) {
                 const int r = a - 3;
                 if (r >= y0 - 2 && r <= y1 + 1) stage2(fs2, r);
-            }
-            lds_barrier();
-            if (role == 0) {
-                if (a < A1 && (!walls || (a >= 0 && a < ny))) collide(fc, a, 0);
-            } else {
+                lds_barrier();
                 const int c = a - 5;
                 if (c >= y0 && c < y1) collide(fc, c, 1);
+            };
+            for (int a = A0; a <= T1; a += 4) {
+                tick(a, F0, F2);
+                if (a + 1 <= T1) tick(a + 1, F1, F3);
+                if (a + 2 <= T1) tick(a + 2, F2, F0);
+                if (a + 3 <= T1) tick(a + 3, F3, F1);
             }
-        };
-        for (int a = A0; a <= T1; a += 4) {
-            tick(a, F0, F2, F3);
-            if (a + 1 <= T1) tick(a + 1, F1, F3, F0);
-            if (a + 2 <= T1) tick(a + 2, F2, F0, F1);
-            if (a + 3 <= T1) tick(a + 3, F3, F1, F2);
         }
         // wall momentum in FP64, step t's first, then step t+1's (the order
         // of two single steps)

@@ -1,6 +1,8 @@
-"""Full-size checks: the 4096x4096 benchmark workload in the launch shape the
-benchmark times (from the committed tuning cache), against the FP64 oracle on
-sampled windows, and through properties that hold at any size.
+"""Full-size checks: the 4096x4096 benchmark workload in the launch
+configuration the benchmark times (shape from the committed tuning cache; the
+FP32 headline with two time steps per pass, the FP32 single-step variant and
+the other storage forms), against the FP64 oracle on sampled windows, and
+through properties that hold at any size.
 
 Windowed parity: after k steps a site depends only on the initial state
 within distance 3k (one site of streaming plus two of the force stencil per
@@ -29,6 +31,7 @@ def big():
     ux, uy = inputs.couette(N, N, U, -U)
     lat = lb.Lattice(N, N, ra, rb, ux, uy, u_top=U, u_bot=-U, storage="f32", **inputs.COUPLINGS)
     bx, ly, _ = lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
+    lat.set_fusion(2)
     yield lat, ra, rb, ux, uy, (bx, ly)
     lat.close()
 
@@ -77,9 +80,11 @@ def _check_windows(fields, ra, rb, ux, uy, k, tol, label):
 
 
 def test_sampled_windows_match_oracle(big):
+    """The headline: two fused passes (four steps) in the tuned shape."""
     lat, ra, rb, ux, uy, shape = big
-    lat.step(3)
-    _check_windows(lat.fields(), ra, rb, ux, uy, 3, 1e-6, f"f32 {shape}")
+    lat.step(4)
+    assert lat.time() == 4
+    _check_windows(lat.fields(), ra, rb, ux, uy, 4, 1e-6, f"f32 two steps per pass {shape}")
 
 
 # 16-bit deviation storage: every step (and the initialisation) rounds each
@@ -89,15 +94,18 @@ def test_sampled_windows_match_oracle(big):
 # 6.1e-5 + 4 x 1.5e-5 + 4 x 3.8e-6 = 1.4e-4 in FP16; four roundings (init + 3
 # steps) give 5.5e-4, and the bound is taken at 1e-3 to cover the first-order
 # redistribution by the forces.  BF16 has an 8x coarser mantissa: 8e-3.
-@pytest.mark.parametrize("storage,tol", [("f16dev", 1e-3), ("bf16dev", 8e-3), ("mom32", 1e-6)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16dev", 1e-3), ("bf16dev", 8e-3), ("mom32", 1e-6)])
 def test_other_storage_windows_in_bench_shape(big, storage, tol):
-    """The other storage forms the benchmark times, each in its own cached
-    launch shape, on the same windows."""
+    """The other variants the benchmark times (FP32 one step per pass, the
+    16-bit and moment forms), each in its own cached launch shape, on the same
+    windows."""
     from paper_1004_5058_amd import lb
     _, ra, rb, ux, uy, _ = big
     lat = lb.Lattice(N, N, ra, rb, ux, uy, u_top=U, u_bot=-U, storage=storage, **inputs.COUPLINGS)
     try:
         bx, ly, _ = lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
+        if storage == "f32":
+            lat.set_fusion(1)
         lat.step(3)
         _check_windows(lat.fields(), ra, rb, ux, uy, 3, tol, f"{storage} ({bx}, {ly})")
     finally:
@@ -106,16 +114,18 @@ def test_other_storage_windows_in_bench_shape(big, storage, tol):
 
 def test_conservation_and_wall_budget(big):
     """Per-species mass is exact with moving walls, and the fluid's x momentum
-    changes by minus the momentum the walls receive, at the full size."""
+    changes by minus the momentum the walls receive, at the full size, over
+    one fused pass (two steps)."""
     lat = big[0]
     s0 = lat.sums()
     lat.stress_reset()
-    lat.step(1)
+    lat.step(2)
     s1 = lat.sums()
     sb, st, n = lat.stress()
-    assert n == 1
+    assert n == 2
     assert abs(s1[0] - s0[0]) / s0[0] < 1e-7 and abs(s1[1] - s0[1]) / s0[1] < 1e-7
-    f_bot, f_top = sb * N, -st * N           # x momentum received by the walls this step
+    # x momentum received by the walls over the two steps (stresses are means per step)
+    f_bot, f_top = sb * N * n, -st * N * n
     budget = (s1[2] - s0[2]) + (f_bot + f_top)
     print(f"dPx {s1[2] - s0[2]:.6e}, walls {f_bot + f_top:.6e}, residual {budget:.3e}")
     assert abs(budget) < 1e-3 * max(abs(f_bot), abs(f_top), 1.0)
