@@ -28,9 +28,12 @@ region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
 flow-curve points per hour on the batched 48-lattice ensemble (10 000 steps
 each) against a plain one-lattice-at-a-time loop; a third leg counts
 stress-controlled flow-curve points per hour with and without the surrogate.
+With --knee, a network trained on 2000 ensemble lattices proposes flow-curve
+refinements near the yield stress, each checked by a 1024x512 lattice run.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--variants f32,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve] [--no-tune]
+       [--variants f32x2,f32,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve] [--no-tune]
+       [--no-surrogate] [--knee]
 """
 import argparse
 import hashlib
@@ -266,6 +269,9 @@ def main():
     ap.add_argument("--flow-steps", type=int, default=10000)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the stress-controlled surrogate leg")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
+    ap.add_argument("--knee", action="store_true",
+                    help="add the knee-refinement leg: a network trained on 2000 ensemble lattices proposes "
+                         "refinements near the yield stress, each checked by a 1024x512 lattice run (minutes)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"))
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
@@ -351,6 +357,14 @@ def main():
             line["surrogate"] = surrogate_rates()
         except Exception as e:  # reported, never hidden
             line["surrogate"] = {"error": repr(e)}
+    if a.knee:
+        from paper_1004_5058_amd import surrogate
+        try:
+            line["knee_refinement"] = surrogate.knee_refinement(
+                couplings=((-9.0, 8.1), (-9.2, 8.0), (-8.8, 7.7)),
+                log=lambda m: print(f"# knee refinement: {m}", file=sys.stderr, flush=True))
+        except Exception as e:  # reported, never hidden
+            line["knee_refinement"] = {"error": repr(e)}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n)
         line["cpu_baseline"]["single_thread"] = cpu_single_thread()

@@ -92,10 +92,13 @@ class FlowSurrogate:
     def knee(self, g1, g2, S_lo, S_hi, n=400):
         """Shear rate where the fitted Herschel-Bulkley power term equals the
         yield stress (the crossover from yield-dominated to flow-dominated
-        stress) on the surrogate's flow curve, and the fit itself."""
+        stress) on the surrogate's flow curve, and the fit itself.  A curve
+        without a yield stress (below 1e-9 of its largest stress: round-off of
+        the fit) has no knee; the middle of the range is returned."""
         S = np.logspace(np.log10(S_lo), np.log10(S_hi), n)
-        fit = flowcurve.hb_fit(S, self.predict(g1, g2, S))
-        if fit["sigma_y"] <= 0 or fit["B"] <= 0:
+        sig = self.predict(g1, g2, S)
+        fit = flowcurve.hb_fit(S, sig)
+        if fit["sigma_y"] <= 1e-9 * float(np.max(np.abs(sig))) or fit["B"] <= 0:
             return float(np.sqrt(S_lo * S_hi)), fit
         sk = (fit["sigma_y"] / fit["B"]) ** (1.0 / fit["beta"])
         return float(np.clip(sk, S_lo, S_hi)), fit
@@ -132,6 +135,62 @@ def lb_flow_points(S_list, g1, g2, steps, ny=512, nx=1024, seed=500, storage="f3
     specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
     return flowcurve.run_batched(specs, steps, storage=storage)
 
+
+
+def knee_refinement(n_train=2000, steps=10000, couplings=((-9.0, 8.1),), k=6, width=1.0, train_storage="mom32",
+                    check_nx=1024, check_ny=512, heights=(256, 384, 512, 768, 1024), seed=100, iters=4000,
+                    lr=3e-3, tol=0.01, log=None):
+    """Refinement of fixed-coupling flow curves near the yield stress, proposed
+    by a network trained on the batched ensemble and checked by lattice runs.
+
+    n_train lattices drawn like the batched flow-curve ensemble (heights,
+    width 2H, wall speeds log-uniform in [1e-4, 5e-2], G^r and G^a uniform)
+    run `steps` steps in batches (storage `train_storage`; the moment form is
+    exact at tau = 1); every tenth row is held out, the rest train the network.
+    For each (G^a, G^r) in `couplings` the network's flow curve over the
+    ensemble's range of nominal rates is fitted (Herschel-Bulkley), k rates
+    log-spaced within +-width decades of its knee are proposed, and each is
+    checked by a check_nx x check_ny population-form (FP32) lattice run of the
+    same length.  A proposal is accepted when the network's stress is within
+    tol of the lattice's.  Returns the errors, counts and wall times."""
+    t0 = time.perf_counter()
+    rows, t_ens = ensemble_points(n_train, steps, seed=seed, heights=heights, storage=train_storage, log=log)
+    train = [r for i, r in enumerate(rows) if i % 10]
+    held = rows[::10]
+    surr = FlowSurrogate(max_rows=max(len(train), 1), seed=0)
+    loss, t_fit = surr.fit(train, iters=iters, lr=lr)
+    g1h = np.array([r["g_aa1"] for r in held])
+    g2h = np.array([r["g_aa2"] for r in held])
+    Sh = np.array([r["S"] for r in held])
+    sh = np.array([r["sigma"] for r in held])
+    e_held = np.abs(surr.predict(g1h, g2h, Sh) - sh) / np.maximum(np.abs(sh), 1e-300)
+    S_all = np.array([r["S"] for r in rows])
+    S_lo, S_hi = float(S_all.min()), float(S_all.max())
+    curves, t_chk, accepted, total = [], 0.0, 0, 0
+    for c, (g1, g2) in enumerate(couplings):
+        S_prop, fit = surr.propose(g1, g2, S_lo, S_hi, k=k, width=width)
+        pred = surr.predict(g1, g2, S_prop)
+        lb_rows, w = lb_flow_points(S_prop, g1, g2, steps, ny=check_ny, nx=check_nx, seed=seed + 10000 + 100 * c)
+        t_chk += w
+        lbs = np.array([r["sigma"] for r in lb_rows])
+        err = np.abs(pred - lbs) / np.maximum(np.abs(lbs), 1e-300)
+        ok = int(np.sum(err <= tol))
+        accepted += ok
+        total += len(S_prop)
+        curves.append(dict(g_aa1=g1, g_aa2=g2, knee_S=float(surr.knee(g1, g2, S_lo, S_hi)[0]),
+                           hb_network=fit, S=[float(x) for x in S_prop], sigma_network=[float(x) for x in pred],
+                           sigma_lattice=[float(x) for x in lbs], rel_err=[float(x) for x in err],
+                           accepted=ok, hb_lattice=flowcurve.hb_fit(S_prop, lbs) if len(S_prop) >= 3 else None))
+        if log:
+            log(f"coupling ({g1}, {g2}): knee {curves[-1]['knee_S']:.3e}, errors "
+                + ", ".join(f"{x:.3f}" for x in err))
+    wall = time.perf_counter() - t0
+    return dict(train_lattices=len(train), held_out=len(held), steps=steps, train_storage=train_storage,
+                check_lattice=f"{check_nx}x{check_ny}", S_range=[S_lo, S_hi], train_loss=float(loss),
+                held_out_rel_err_median=float(np.median(e_held)), held_out_rel_err_p90=float(np.quantile(e_held, 0.9)),
+                ensemble_s=round(t_ens, 2), train_s=round(t_fit, 2), check_s=round(t_chk, 2), wall_s=round(wall, 2),
+                proposals=total, accepted=accepted, points_per_hour=round(accepted * 3600.0 / wall, 1),
+                curves=curves)
 
 
 class RateSolver:
