@@ -341,8 +341,10 @@ def main():
     from paper_1004_5058_amd import lb
     cp = lb.copy_peak()
     per_launch = STEPS_PER_LAUNCH.get(head, 1)
-    line["hbm"] = {"measured_gbs": None if traffic is None
-                   else round(traffic / (per_launch * r["ms_kernel"] * 1e-3) / 1e9, 1),
+    measured = None if traffic is None else traffic / (per_launch * r["ms_kernel"] * 1e-3) / 1e9
+    line["hbm"] = {"measured_gbs": None if measured is None else round(measured, 1),
+                   "measured_frac_of_peak": None if measured is None else round(measured / HBM_PEAK_GBS, 4),
+                   "measured_frac_of_copy_peak": None if measured is None else round(measured / cp, 4),
                    "steps_per_launch": per_launch,
                    "copy_peak_gbs": round(cp, 1), "frac_of_copy_peak": round(achieved / cp, 4),
                    "copy": "library streaming copy, 16 B per lane, 2 GiB read + 2 GiB written"}

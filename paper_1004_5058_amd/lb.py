@@ -298,7 +298,7 @@ class Lattice:
         _check(_lib.lb_set_graph(self._h, int(steps_per_graph)))
 
     def set_fusion(self, steps_per_pass, ly2=0):
-        """1 or 2 time steps per pass of the step kernel (2: FP32/16-bit storage, no profile)."""
+        """1 or 2 time steps per pass of the step kernel (2: FP32 storage without the line profile)."""
         _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def autotune(self, cache_path=None, steps=20):
@@ -420,7 +420,7 @@ class Batch:
         _check(_lib.lbb_set_graph(self._h, int(steps_per_graph)))
 
     def set_fusion(self, steps_per_pass, ly2=0):
-        """1 or 2 time steps per pass of the step kernel (2: FP32/16-bit storage, no profile)."""
+        """1 or 2 time steps per pass of the step kernel (2: FP32 storage without the line profile)."""
         _check(_lib.lbb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def time_steps(self, n):
