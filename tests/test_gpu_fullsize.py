@@ -94,16 +94,21 @@ def test_sampled_windows_match_oracle(big):
 # 6.1e-5 + 4 x 1.5e-5 + 4 x 3.8e-6 = 1.4e-4 in FP16; four roundings (init + 3
 # steps) give 5.5e-4, and the bound is taken at 1e-3 to cover the first-order
 # redistribution by the forces.  BF16 has an 8x coarser mantissa: 8e-3.
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16dev", 1e-3), ("bf16dev", 8e-3), ("mom32", 1e-6)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16dev", 1e-3), ("bf16dev", 8e-3), ("mom32", 1e-6),
+                                         ("f64", 1e-12)])
 def test_other_storage_windows_in_bench_shape(big, storage, tol):
     """The other variants the benchmark times (FP32 one step per pass, the
     16-bit and moment forms), each in its own cached launch shape, on the same
-    windows."""
+    windows; and FP64 in the default shape (the reference of the full-length
+    runs)."""
     from paper_1004_5058_amd import lb
     _, ra, rb, ux, uy, _ = big
     lat = lb.Lattice(N, N, ra, rb, ux, uy, u_top=U, u_bot=-U, storage=storage, **inputs.COUPLINGS)
     try:
-        bx, ly, _ = lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
+        if storage == "f64":
+            bx, ly = "default", "default"
+        else:
+            bx, ly, _ = lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
         if storage == "f32":
             lat.set_fusion(1)
         lat.step(3)

@@ -9,14 +9,14 @@ perturbation of the start moves the averaged stress by ~1e-8, one of 1e-4 by
 ~3e-5), so the time average is well conditioned and the storage forms can be
 compared with it.
 
-Bounds: the FP32 storage rounds every population once per step (half an ulp,
-2^-24 relative); in a contracting flow these errors add at most linearly, so
-20 000 steps bound the averaged stress's relative error by 20 000 x 2^-24 =
-1.2e-3.  The two FP64 forms differ only by rounding order: 1e-10 bounds 20 000
-steps of ~1e-16 per step with room.  The 16-bit deviation forms are reported
-(the error of each result against FP64 is stated) and bounded loosely: FP16 2
-%, BF16 20 % (an 8-bit mantissa does not resolve the stress, a small
-difference of large momentum fluxes)."""
+Bounds: the two FP64 forms differ only by rounding order: 1e-10 bounds 20 000
+steps of ~1e-16 per step with room.  The averaged stress is a small difference
+of large momentum fluxes (at wall speed 0.05 it is ~1e-3 of the diagonal
+populations whose difference makes it), so the storage rounding of the
+populations reaches its relative error amplified; no useful bound follows from
+the arithmetic, and the reduced-precision errors are stated (printed; the
+measured values are FP32 1.4e-4 at worst, FP16 6e-3, BF16 0.11) under sanity
+bounds: FP32 2e-3, FP16 2 %, BF16 20 %."""
 import numpy as np
 import pytest
 
@@ -25,7 +25,7 @@ from paper_1004_5058_amd import inputs
 
 pytestmark = pytest.mark.gpu
 N, U, STEPS = 1024, 0.05, 20000
-BOUND = {"mom64": 1e-10, "f32": 1.2e-3, "f32x2": 1.2e-3, "mom32": 1.2e-3, "f16dev": 2e-2, "bf16dev": 2e-1}
+BOUND = {"mom64": 1e-10, "f32": 2e-3, "f32x2": 2e-3, "mom32": 2e-3, "f16dev": 2e-2, "bf16dev": 2e-1}
 
 
 def _run(storage, fusion=1):
@@ -59,3 +59,60 @@ def test_time_averaged_wall_stress_1024_full_length():
         assert np.all(e < BOUND[k]), (k, e)
     # two steps per pass is bitwise the single-step run
     np.testing.assert_array_equal(out["f32x2"], out["f32"])
+
+
+# The 4096 x 4096 workload at its stated length (wall speed 0.02, 5000 steps):
+# fields at the end and the wall stress averaged over the second half, each
+# storage form against the GPU's FP64 step (whose full-size windows match the
+# oracle, tests/test_gpu_fullsize.py).  Fields, FP32: each population is
+# rounded once per step (2^-24 relative); added linearly over 5000 steps that
+# is 3e-4 of the largest density (and of the momentum scale).  The averaged
+# stress (~6e-6 here, ~1e-4 of the populations it is made from) and the 16-bit
+# forms are stated, under sanity bounds (FP32 stress 2e-3; FP16 5e-2; BF16 0.5
+# for fields and 1 for the stress: measured 0.24 and 0.47, the BF16 form does
+# not hold the interfaces of this run).
+N4, U4, STEPS4 = 4096, 0.02, 5000
+FIELD_BOUND = {"f32x2": 3e-4, "mom32": 3e-4, "f16dev": 5e-2, "bf16dev": 5e-1}
+STRESS_BOUND = {"f32x2": 2e-3, "mom32": 2e-3, "f16dev": 5e-2, "bf16dev": 1.0}
+
+
+def _run4(storage, fusion=1):
+    from paper_1004_5058_amd import lb
+    ra, rb = inputs.emulsion(N4, N4, seed=1)
+    ux, uy = inputs.couette(N4, N4, U4, -U4)
+    lat = lb.Lattice(N4, N4, ra, rb, ux, uy, u_top=U4, u_bot=-U4, storage=storage, **inputs.COUPLINGS)
+    del ra, rb, ux, uy
+    try:
+        if fusion > 1:
+            lat.set_fusion(fusion)
+        lat.step(STEPS4 // 2)
+        lat.stress_reset()
+        lat.step(STEPS4 // 2)
+        sb, st, n = lat.stress()
+        assert n == STEPS4 // 2
+        a, b, vx, vy = lat.fields()
+        return (a, b, vx * (a + b), vy * (a + b)), np.array([sb, st, 0.5 * (sb + st)])
+    finally:
+        lat.close()
+
+
+def test_4096_fields_and_stress_full_length():
+    need_gpu()
+    (ra, rb, jx, jy), sref = _run4("f64")
+    scale_r = max(ra.max(), rb.max())
+    scale_j = (ra + rb).max() / np.sqrt(3.0)
+    print(f"\nFP64 reference after {STEPS4} steps: stress bot {sref[0]:.9e}, top {sref[1]:.9e}")
+    errs = {}
+    for storage in ("f32x2", "mom32", "f16dev", "bf16dev"):
+        name = "f32" if storage == "f32x2" else storage
+        (a, b, x, y), s = _run4(name, fusion=2 if storage == "f32x2" else 1)
+        e_rho = max(np.abs(a - ra).max(), np.abs(b - rb).max()) / scale_r
+        e_j = max(np.abs(x - jx).max(), np.abs(y - jy).max()) / scale_j
+        e_s = np.abs(s - sref) / np.abs(sref)
+        del a, b, x, y
+        errs[storage] = (e_rho, e_j, e_s)
+        print(f"{storage:8s}: rho {e_rho:.2e}, j {e_j:.2e} (bound {FIELD_BOUND[storage]:g}), stress bot "
+              f"{e_s[0]:.2e} top {e_s[1]:.2e} mean {e_s[2]:.2e} (bound {STRESS_BOUND[storage]:g})")
+    for storage, (e_rho, e_j, e_s) in errs.items():
+        assert e_rho < FIELD_BOUND[storage] and e_j < FIELD_BOUND[storage], storage
+        assert np.all(e_s < STRESS_BOUND[storage]), storage
