@@ -1036,6 +1036,22 @@ __device__ __forceinline__ int col_of(int x, int q, int nx)
     return c < 0 ? c + nx : (c >= nx ? c - nx : c);
 }
 
+// One rounding, to nearest-even, of an FP64 value to the storage format.  The
+// 16-bit formats pass through FP32 rounded to odd (truncated, last bit set if
+// anything was cut off): with at least two more significant bits than the
+// target, that leaves a single correct rounding (Boldo and Melquiond, rounding
+// to odd, IEEE Trans. Computers 57(4), 2008); a plain FP32 step would round
+// twice.
+template <class S> __device__ __forceinline__ S to_storage(double x) { return (S)x; }
+__device__ __forceinline__ float odd_f32(double x)
+{
+    float t = __double2float_rz(x);
+    if ((double)t != x) t = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, t) | 1u);
+    return t;
+}
+template <> __device__ __forceinline__ _Float16 to_storage<_Float16>(double x) { return (_Float16)odd_f32(x); }
+template <> __device__ __forceinline__ __bf16 to_storage<__bf16>(double x) { return (__bf16)odd_f32(x); }
+
 // f_is(r, 0) = f^eq_i(rho_s(r), u(r)), evaluated in FP64 and rounded once to
 // the storage format.
 template <class P>
@@ -1044,7 +1060,6 @@ __global__ void k_init(char* __restrict__ base, const LatDesc* __restrict__ dd, 
                        const double* __restrict__ ux, const double* __restrict__ uy)
 {
     using S = typename P::S;
-    using C = typename P::C;
     const LatDesc& d = *dd;
     const long long n = (long long)d.nx * d.ny;
     const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
@@ -1060,7 +1075,7 @@ __global__ void k_init(char* __restrict__ base, const LatDesc* __restrict__ dd, 
             for (int i = 0; i < 9; ++i) {
                 const double cu = CX[i] * u + CY[i] * v;
                 const double feq = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-                out[(9 * s + i) * d.plane + col_of(x, i, d.nx)] = (S)(C)(feq - d.wref[9 * s + i]);
+                out[(9 * s + i) * d.plane + col_of(x, i, d.nx)] = to_storage<S>(feq - d.wref[9 * s + i]);
             }
         }
     }
