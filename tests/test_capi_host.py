@@ -143,3 +143,29 @@ def test_state_buffers_hold_the_fp64_staging(storage, nx, ny):
     lb.load_library()
     n = lb.lb_state_bytes(lb.make_params(nx, ny, tau=1.0, storage=storage))
     assert n >= 2 * 32 * nx * ny
+
+
+def test_last_error_is_per_thread():
+    """lb_last_error is thread-local: two threads that fail validation in
+    different ways, both before either reads its message, each read their own."""
+    import threading
+    from paper_1004_5058_amd import lb
+    L = lb.load_library()
+    gate = threading.Barrier(2)
+    out = {}
+
+    def worker(name, kw):
+        p = lb.make_params(64, 64, **kw)
+        n = ctypes.c_size_t()
+        code = L.lb_state_bytes(ctypes.byref(p), ctypes.byref(n))
+        gate.wait()                    # both errors are set before either message is read
+        out[name] = (code, L.lb_last_error().decode())
+
+    threads = [threading.Thread(target=worker, args=("tau", dict(tau=0.4))),
+               threading.Thread(target=worker, args=("rho0", dict(rho0=-1.0)))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=30)
+    assert out["tau"][0] == -1 and "tau" in out["tau"][1] and "rho0" not in out["tau"][1]
+    assert out["rho0"][0] == -1 and "rho0" in out["rho0"][1] and "tau" not in out["rho0"][1]
