@@ -116,6 +116,19 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
                 shape=None if shape is None else {"bx": shape[0], "ly": shape[1]})
 
 
+def _batch_passes(tune_cache, storage, n, sites):
+    """Steps per pass and fused tile height the tuning cache holds for a batch
+    (keys end in <storage>/batch<n>_<sites>)."""
+    try:
+        with open(tune_cache) as f:
+            entries = json.load(f)
+    except (TypeError, OSError, ValueError):
+        return {}
+    suffix = f"/{storage}/batch{n}_{sites}"
+    e = next((v for k, v in entries.items() if k.endswith(suffix)), {})
+    return {"steps_per_pass": e.get("fusion", 1), "ly2": e.get("ly2", 0)} if e else {}
+
+
 def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     """Flow-curve points per hour on the batched ensemble (48 lattices, heights
     256..1024, width 2H, U log-uniform in [1e-4, 5e-2], G^r in [7.5, 8.5]):
@@ -130,12 +143,13 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
     sites = sum(s["nx"] * s["ny"] for s in specs)
     if tune_cache is not None:
+        # tuned before the timed run; the run applies the cached entry
         b = lb.Batch(specs, storage="f32", profile=True)
         tuned = b.autotune(tune_cache, steps=3)
         b.close()
     else:
         tuned = (0, 0, 0, 0.0)
-    rows_b, wall_b = flowcurve.run_batched(specs, steps, bx=tuned[0], ly=tuned[1], grid=tuned[2])
+    rows_b, wall_b = flowcurve.run_batched(specs, steps, tune_cache=tune_cache)
     print(f"# flow curve: batched {n_lat} lattices x {steps} steps in {wall_b:.2f} s", file=sys.stderr, flush=True)
     rows_p, wall_p = flowcurve.run_plain(specs, steps, tune_cache=tune_cache)
     print(f"# flow curve: plain loop in {wall_p:.2f} s", file=sys.stderr, flush=True)
@@ -147,7 +161,7 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
         b.close()
     else:
         tm = (0, 0, 0, 0.0)
-    rows_m, wall_m = flowcurve.run_batched(specs, steps, storage="mom32", bx=tm[0], ly=tm[1], grid=tm[2])
+    rows_m, wall_m = flowcurve.run_batched(specs, steps, storage="mom32", tune_cache=tune_cache)
     print(f"# flow curve: batched moment form in {wall_m:.2f} s", file=sys.stderr, flush=True)
     agree_m = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_m, rows_b))
     return dict(lattices=n_lat, steps=steps, sites=sites,
@@ -161,7 +175,8 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
                 batched_mlups=round(sites * steps / wall_b / 1e6, 1),
                 plain_mlups=round(sites * steps / wall_p / 1e6, 1),
                 speedup=round(wall_p / wall_b, 3), max_sigma_mismatch=agree,
-                launch_shape={"bx": tuned[0], "ly": tuned[1], "grid": tuned[2]})
+                launch_shape=dict({"bx": tuned[0], "ly": tuned[1], "grid": tuned[2]},
+                                  **_batch_passes(tune_cache, "f32", n_lat, sites)))
 
 
 def surrogate_rates(n_train=512, n_cases=10, storage="f32", plain=True):

@@ -177,10 +177,12 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
  * or 2.  With 2, lb_step advances pairs of steps (Eq. (1) applied twice) with
  * one kernel that keeps the intermediate populations in on-chip memory, so
  * each population crosses HBM once per two updates; an odd remaining step
- * runs alone.  The results are bitwise those of single steps.  Tiles of 250
- * columns x ly2 rows (ly2 = 0: the smallest height that leaves at most one
- * tile per compute unit).  LB_EINVAL unless the storage is LB_F32, the
- * profile accumulators are off and the device grants the kernel's shared
+ * runs alone.  Populations and wall stress are bitwise those of single
+ * steps; the line profile (lb_profile), when on, is accumulated too, from
+ * partial sums grouped by the fused kernel's tiles, so it agrees with single
+ * steps to FP64 rounding.  Tiles of 250 columns x ly2 rows (ly2 = 0: the
+ * smallest height that leaves at most one tile per compute unit).  LB_EINVAL
+ * unless the storage is LB_F32 and the device grants the kernel's shared
  * memory (about 125 KiB per block). */
 lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
 
@@ -195,8 +197,8 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
  * {64, 128, 256, 512} as lb_set_launch admits them, ly in {8..256}, shapes
  * within the device's shared memory per block; for batches also persistent grids of 1, 2
  * and 4 blocks per compute unit) on this lattice; where lb_set_fusion admits
- * two steps per pass (FP32, no profile), also that mode behind the best
- * shape.  Applies the fastest (shape and steps per pass; *ms is its time per
+ * two steps per pass (FP32), also that mode behind the best shape, at the
+ * automatic tile height and at 64, 128 and 256 rows.  Applies the fastest (shape and steps per pass; *ms is its time per
  * step) and restores the simulation state exactly (populations, accumulators,
  * step count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid,
  * fusion, ly2, ms}}, key "<gfx arch>/<storage>/<nx>x<ny>" (batches:

@@ -97,11 +97,14 @@ lb_status validate(const lb_params* p, int storage0)
 
 struct Lat {
     lb_params p;
-    int pitch = 0, ngroups = 0;
+    int pitch = 0, ngroups = 0, ngroups2 = 0;   // profile partial rows: single-step, fused
     long long plane = 0;
     size_t off_f[2] = {0, 0}, off_stress = 0, off_prof = 0, off_body = 0, end = 0;
     double rho_ref[2] = {0, 0};
 };
+
+// FP64 entries of a lattice's profile accumulators (when enabled).
+size_t prof_entries(const Lat& a) { return (size_t)(a.ngroups + a.ngroups2) * (size_t)a.p.ny; }
 
 // Layout: [descs][partials][results][item table] then per lattice
 // [f0][f1][stress][prof][body force per row].
@@ -139,6 +142,9 @@ Layout plan(std::vector<Lat>& lats)
         // profile accumulator rows: one per 64 columns, or for the moment form
         // one per tile of the narrowest launch shape (60 collided columns)
         a.ngroups = is_mom(a.p.storage) ? (a.p.nx + 59) / 60 : (a.p.nx + 63) / 64;
+        // and, for FP32 populations, the fused two-step kernel's partials:
+        // two steps x strips of TW2 columns x four waves
+        a.ngroups2 = a.p.storage == LB_F32 ? 8 * ((a.p.nx + lbk::TW2 - 1) / lbk::TW2) : 0;
         // Each state buffer also serves as staging for four FP64 arrays of
         // nx*ny values (initial fields, field reads): at least 32 bytes per
         // site, whatever the storage needs (6 FP32 moments need only 24).
@@ -148,7 +154,7 @@ Layout plan(std::vector<Lat>& lats)
         a.off_f[1] = off + fbytes;
         a.off_stress = off + 2 * fbytes;
         a.off_prof = a.off_stress + align_up(sizeof(double) * 2 * a.p.nx, ALIGN);
-        const size_t pbytes = a.p.profile ? align_up(sizeof(double) * (size_t)a.ngroups * a.p.ny, ALIGN) : 0;
+        const size_t pbytes = a.p.profile ? align_up(sizeof(double) * prof_entries(a), ALIGN) : 0;
         a.off_body = a.off_prof + pbytes;
         const size_t bbytes = a.p.fx_amp != 0.0 ? align_up(sizeof(double) * (size_t)a.p.ny, ALIGN) : 0;
         a.end = a.off_body + bbytes;
@@ -173,6 +179,7 @@ void fill_desc(const Lat& a, lbk::LatDesc& d)
     d.pitch = a.pitch;
     d.walls = p.walls_y;
     d.ngroups = a.ngroups;
+    d.ngroups2 = a.ngroups2;
     d.tau = p.tau;
     d.omega = 1.0 / p.tau;
     d.rho0 = p.rho0;
@@ -484,7 +491,7 @@ lb_status reset_acc(lbb_handle* h)
     for (const Lat& a : h->lats) {
         HIP_TRY(lbk::launch_fill((double*)(h->base + a.off_stress), 2ll * a.p.nx, 0.0, h->stream));
         if (a.p.profile)
-            HIP_TRY(lbk::launch_fill((double*)(h->base + a.off_prof), (long long)a.ngroups * a.p.ny, 0.0,
+            HIP_TRY(lbk::launch_fill((double*)(h->base + a.off_prof), (long long)prof_entries(a), 0.0,
                                      h->stream));
     }
     h->nsamples = 0;
@@ -731,16 +738,14 @@ lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
     return decompose(h);
 }
 
-// Two time steps per pass (k_step2): FP32 population storage, no profile
-// accumulators.  ly2 = 0 picks the tile height.
+// Two time steps per pass (k_step2): FP32 population storage.  ly2 = 0 picks
+// the tile height.
 lb_status set_fusion(lbb_handle* h, int k, int ly2)
 {
     if (k != 1 && k != 2) return fail(LB_EINVAL, "steps per pass must be 1 or 2");
     if (ly2 < 0) return fail(LB_EINVAL, "ly2 must be >= 0");
     if (k == 2) {
         if (h->storage != LB_F32) return fail(LB_EINVAL, "two steps per pass need FP32 population storage");
-        for (const Lat& a : h->lats)
-            if (a.p.profile) return fail(LB_EINVAL, "two steps per pass keep no profile accumulators");
         int dev = 0, lim = 65536;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
@@ -797,14 +802,8 @@ struct TuneEntry {
     double ms = 0;
 };
 
-// Whether the handle may run two steps per pass (set_fusion's conditions).
-bool fusion_allowed(const lbb_handle* h)
-{
-    if (h->storage != LB_F32) return false;
-    for (const Lat& a : h->lats)
-        if (a.p.profile) return false;
-    return true;
-}
+// Whether the handle may run two steps per pass (set_fusion's storage condition).
+bool fusion_allowed(const lbb_handle* h) { return h->storage == LB_F32; }
 
 std::string arch_name()
 {
@@ -950,15 +949,20 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
         }
         if (st != LB_OK) break;
     }
-    // two steps per pass, automatic tile height, behind the best single-step
-    // shape (which any odd remaining step uses)
+    // two steps per pass behind the best single-step shape (which any odd
+    // remaining step uses): the automatic tile height (about one tile per
+    // CU) and shorter tiles, which balance batches of uneven lattices
     if (st == LB_OK && best.bx && fusion_allowed(h)) {
         st = set_launch(h, best.bx, best.ly, best.grid);
-        if (st == LB_OK) st = set_fusion(h, 2, 0);
-        if (st == LB_OK) st = steps_direct_warm(h, 2);
-        double ms = 0;
-        if (st == LB_OK) st = time_steps(h, steps + (steps & 1), &ms);
-        if (st == LB_OK && ms < best.ms) { best.fusion = 2; best.ly2 = 0; best.ms = ms; }
+        for (int ly2 : {0, 64, 128, 256}) {
+            if (st != LB_OK) break;
+            if (ly2 && ly2 >= maxny) continue;
+            st = set_fusion(h, 2, ly2);
+            if (st == LB_OK) st = steps_direct_warm(h, 2);
+            double ms = 0;
+            if (st == LB_OK) st = time_steps(h, steps + (steps & 1), &ms);
+            if (st == LB_OK && ms < best.ms) { best.fusion = 2; best.ly2 = ly2; best.ms = ms; }
+        }
         h->fusion = 1;
     }
     // restore the state
@@ -1174,7 +1178,7 @@ lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
     const Lat& a = b->lats[0];
     const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
     const size_t sbb = 2ull * a.p.nx * sizeof(double);
-    const size_t pb = a.p.profile ? (size_t)a.ngroups * a.p.ny * sizeof(double) : 0;
+    const size_t pb = a.p.profile ? prof_entries(a) * sizeof(double) : 0;
     const size_t need = sizeof(CkptHeader) + fb + sbb + pb;
     if (!buf) { *bytes = need; return LB_OK; }
     if (*bytes < need) return fail(LB_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
@@ -1217,7 +1221,7 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes)
     // the section sizes must be exactly this lattice's (they bound the copies below)
     const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
     const size_t sbb = 2ull * a.p.nx * sizeof(double);
-    const size_t pb = a.p.profile ? (size_t)a.ngroups * a.p.ny * sizeof(double) : 0;
+    const size_t pb = a.p.profile ? prof_entries(a) * sizeof(double) : 0;
     if (hd.fbytes != fb || hd.sbytes != sbb || hd.pbytes != pb)
         return fail(LB_ESTATE, "checkpoint section sizes do not match this lattice");
     if (bytes < sizeof hd + hd.fbytes + hd.sbytes + hd.pbytes) return fail(LB_EINVAL, "truncated checkpoint");

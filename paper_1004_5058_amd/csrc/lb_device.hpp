@@ -12,14 +12,16 @@ struct LatDesc {
     long long off_f[2];    // byte offsets (from the state base) of the two population buffers,
                            // layout [s][i][y][pitch]
     long long off_stress;  // [2][nx] FP64: x momentum received by bottom / top wall, summed over steps
-    long long off_prof;    // [ngroups][ny] FP64: sum over steps of per-64-column sums of u_x; < 0: off
+    long long off_prof;    // [ngroups + ngroups2][ny] FP64: sums over steps of partial row sums of u_x
+                           // (per 64 columns, then the fused kernel's per step, strip and wave); < 0: off
     long long off_body;    // [ny] FP64: external body force F_x(y) of each row; < 0: none
     long long plane;       // elements per (species, direction) plane = ny * pitch
     int nx, ny, pitch, walls;
     int item_begin;        // first global work item of this lattice (multiple of 8)
     int nitems;            // nstrip * nseg
     int nstrip, nseg, ly;  // tiles: strips of bx columns, segments of ly rows
-    int ngroups;           // ceil(nx / 64)
+    int ngroups;           // ceil(nx / 64) (moment form: ceil(nx / 60))
+    int ngroups2;          // partial sums of the fused two-step kernel: 2 steps x nstrip2 x 4 waves (else 0)
     // Tiles of the fused two-step kernel: strips of 250 columns, segments of
     // ly2 rows, items item_begin2 .. item_begin2 + nitems2 - 1 of its own table.
     int item_begin2, nitems2, nstrip2, nseg2, ly2;

@@ -788,6 +788,10 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const int ndma = 4;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
+        // line profile: each wave adds the sum of u_x over its own columns of
+        // every collided row of this tile to its partial, per step
+        double* __restrict__ prof2 =
+            d.off_prof >= 0 ? (double*)(base + d.off_prof) + (long long)d.ngroups * ny : nullptr;
         C mom_b = 0, mom_t = 0;
 
         using R = Row<P>;
@@ -895,6 +899,11 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             const C ux = jx * inv_rho, uy = jy * inv_rho;
             const int yw = (y < 0) ? y + ny : (y >= ny ? y - ny : y);   // periodic image of a step-t row
             const C gx = (body != nullptr) ? (C)body[yw] * inv_rho : (C)0;
+            if (prof2 != nullptr && y >= y0 && y < y1) {
+                double su = own ? (double)ux : 0.0;
+                su = wave_sum(su);
+                if (lane == 0) prof2[((long long)(k * nstrip + strip) * 4 + wave) * ny + y] += su;
+            }
             const bool bot = walls && (y == 0);
             const bool top = walls && (y == ny - 1);
             const bool count = own && y >= y0 && y < y1;   // wall momentum owned by this tile
@@ -1280,7 +1289,7 @@ __global__ void k_profile_reduce(char* __restrict__ base, const LatDesc* __restr
     const double* pr = (const double*)(base + d.off_prof);
     for (int y = blockIdx.x * blockDim.x + threadIdx.x; y < d.ny; y += gridDim.x * blockDim.x) {
         double s = 0;
-        for (int g = 0; g < d.ngroups; ++g) s += pr[(long long)g * d.ny + y];
+        for (int g = 0; g < d.ngroups + d.ngroups2; ++g) s += pr[(long long)g * d.ny + y];
         out[y] = s;
     }
 }

@@ -101,17 +101,22 @@ def lattice_specs(draws, couplings, init="emulsion"):
     return specs
 
 
-def run_batched(specs, steps, storage="f32", average_from=None, bx=0, ly=0, grid=0, graph=32):
+def run_batched(specs, steps, storage="f32", average_from=None, bx=0, ly=0, grid=0, graph=32, tune_cache=None):
     """Advance all lattices together (one step kernel per time step, HIP
     graphs); average the stress and profile over the last steps - average_from
-    steps (default: the second half)."""
+    steps (default: the second half).  With tune_cache, the batch takes its
+    launch shape and steps per pass from the autotuner (a cached entry is
+    applied without timing; tune beforehand to keep tuning out of the run),
+    else the given shape."""
     import torch
     from . import lb
     if average_from is None:
         average_from = steps // 2
     t0 = time.perf_counter()
     b = lb.Batch(specs, storage=storage, profile=True)
-    if bx or ly or grid:
+    if tune_cache is not None:
+        b.autotune(tune_cache, steps=3)
+    elif bx or ly or grid:
         b.set_launch(bx, ly, grid)
     b.set_graph(graph)
     b.step(average_from)
@@ -133,11 +138,12 @@ def run_batched(specs, steps, storage="f32", average_from=None, bx=0, ly=0, grid
 
 
 def run_plain(specs, steps, storage="f32", average_from=None, tune_cache=None):
-    """The same runs one lattice at a time, one kernel launch per step, no
-    graph: the baseline the batched path is measured against.  With
-    tune_cache, every lattice size is autotuned once before the timed loop
-    (results cached in that JSON file) and each lattice runs in the shape of
-    its size; otherwise in the library's default shape."""
+    """The same runs one lattice at a time, one kernel launch per step (or
+    per two steps where the tuner picked that), no graph: the baseline the
+    batched path is measured against.  With tune_cache, every lattice size is
+    autotuned once before the timed loop (results cached in that JSON file)
+    and each lattice applies the cached entry of its size (shape and steps
+    per pass; no timing); otherwise the library's default shape."""
     import torch
     from . import lb
     if average_from is None:
@@ -146,25 +152,26 @@ def run_plain(specs, steps, storage="f32", average_from=None, tune_cache=None):
     def kwargs(s):
         return {k: v for k, v in s.items() if k not in ("nx", "ny", "rho_a", "rho_b", "ux", "uy")}
 
-    shapes = {}
     if tune_cache is not None:
+        tuned = set()
         for s in specs:
             key = (s["nx"], s["ny"])
-            if key in shapes:
+            if key in tuned:
                 continue
             lat = lb.Lattice(s["nx"], s["ny"], s["rho_a"], s["rho_b"], s["ux"], s["uy"], storage=storage,
                              profile=True, **kwargs(s))
             lat.set_graph(0)
-            shapes[key] = lat.autotune(tune_cache, steps=10)[:2]
+            lat.autotune(tune_cache, steps=10)
             lat.close()
+            tuned.add(key)
     t0 = time.perf_counter()
     rows = []
     for s in specs:
         lat = lb.Lattice(s["nx"], s["ny"], s["rho_a"], s["rho_b"], s["ux"], s["uy"], storage=storage,
                          profile=True, **kwargs(s))
-        if shapes:
-            lat.set_launch(*shapes[(s["nx"], s["ny"])])
         lat.set_graph(0)
+        if tune_cache is not None:
+            lat.autotune(tune_cache, steps=10)      # the cached entry of this size
         lat.step(average_from)
         lat.stress_reset()
         lat.step(steps - average_from)

@@ -298,12 +298,12 @@ class Lattice:
         _check(_lib.lb_set_graph(self._h, int(steps_per_graph)))
 
     def set_fusion(self, steps_per_pass, ly2=0):
-        """1 or 2 time steps per pass of the step kernel (2: FP32 storage without the line profile)."""
+        """1 or 2 time steps per pass of the step kernel (2: FP32 population storage)."""
         _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def autotune(self, cache_path=None, steps=20):
-        """Pick the fastest launch shape, and for FP32 without profile the steps per
-        pass (state preserved); returns (bx, ly, ms per step)."""
+        """Pick the fastest launch shape, and for FP32 the steps per pass (state
+        preserved); returns (bx, ly, ms per step)."""
         bx, ly, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         path = cache_path.encode() if cache_path else None
         _check(_lib.lb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(ms)))
@@ -420,7 +420,7 @@ class Batch:
         _check(_lib.lbb_set_graph(self._h, int(steps_per_graph)))
 
     def set_fusion(self, steps_per_pass, ly2=0):
-        """1 or 2 time steps per pass of the step kernel (2: FP32 storage without the line profile)."""
+        """1 or 2 time steps per pass of the step kernel (2: FP32 population storage)."""
         _check(_lib.lbb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def time_steps(self, n):
@@ -429,8 +429,8 @@ class Batch:
         return ms.value
 
     def autotune(self, cache_path=None, steps=10):
-        """Pick the fastest launch shape and grid, and for FP32 without profile the
-        steps per pass (state preserved); returns (bx, ly, grid, ms per step)."""
+        """Pick the fastest launch shape and grid, and for FP32 the steps per pass
+        (state preserved); returns (bx, ly, grid, ms per step)."""
         bx, ly, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         path = cache_path.encode() if cache_path else None
         _check(_lib.lbb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(grid),

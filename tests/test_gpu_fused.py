@@ -105,7 +105,7 @@ def test_fused_batch_equals_single_steps():
 def test_fused_refused_where_not_built():
     from paper_1004_5058_amd import lb
     ra, rb = inputs.noise(64, 16, 1)
-    for storage, kw in (("f64", {}), ("mom32", {}), ("f16dev", {}), ("bf16dev", {}), ("f32", dict(profile=True))):
+    for storage, kw in (("f64", {}), ("mom32", {}), ("f16dev", {}), ("bf16dev", {})):
         lat = gpu_lattice(64, 16, ra, rb, storage=storage, **kw)
         with pytest.raises(lb.LBError, match="two steps per pass"):
             lat.set_fusion(2)
@@ -114,10 +114,11 @@ def test_fused_refused_where_not_built():
 
 
 def test_autotune_considers_two_steps_per_pass(tmp_path):
-    """The tuner also times two steps per pass for an FP32 lattice without
-    profile, applies the faster mode, preserves the state (either mode is
-    bitwise the single-step result) and records the choice in the cache; a
-    profile-enabled lattice of the same key runs one step per pass."""
+    """The tuner also times two steps per pass for an FP32 lattice, applies
+    the faster mode, preserves the state (either mode is bitwise the
+    single-step result) and records the choice in the cache; a profile-enabled
+    lattice of the same key applies the cached entry and accumulates its
+    profile."""
     import json
     nx, ny, u = 1024, 512, 0.02
     ra, rb = inputs.emulsion(nx, ny, seed=3)
@@ -138,3 +139,55 @@ def test_autotune_considers_two_steps_per_pass(tmp_path):
     assert prof.autotune(cache, steps=4)[:2] == (bx, ly)
     prof.step(4)
     assert prof.time() == 4 and prof.profile()[1] == 4
+
+
+@pytest.mark.parametrize("nx,ny,walls,body,ly2", [(600, 300, True, False, 0), (500, 120, False, True, 7),
+                                                   (252, 31, True, True, 1), (1000, 40, True, False, 16)])
+def test_fused_profile_matches_single_steps(nx, ny, walls, body, ly2):
+    """With the line profile on, two steps per pass keep populations and wall
+    stress bitwise and accumulate the profile from the fused tiles' partial
+    sums: equal to the single-step profile to FP64 rounding (the column
+    groups of the partial sums differ), across a stress reset and an odd
+    step count."""
+    res = []
+    for per_pass in (1, 2):
+        ra, rb = inputs.emulsion(nx, ny, seed=5)
+        kw = dict(fx_amp=1e-5, fx_k=2 * np.pi / ny) if body else {}
+        lat = gpu_lattice(nx, ny, ra, rb, walls=walls, u_top=0.02 if walls else 0.0,
+                          u_bot=-0.02 if walls else 0.0, storage="f32", profile=True, **kw)
+        lat.set_fusion(per_pass, ly2)
+        lat.step(10)
+        lat.stress_reset()
+        lat.step(23)
+        res.append((lat.populations(), lat.stress(), lat.profile()))
+        lat.close()
+    (p1, s1, (q1, n1)), (p2, s2, (q2, n2)) = res
+    np.testing.assert_array_equal(p2, p1)
+    assert s2 == s1 and n1 == n2 == 23
+    scale = np.max(np.abs(q1))
+    assert scale > 0
+    assert np.max(np.abs(q2 - q1)) <= 1e-13 * scale, np.max(np.abs(q2 - q1)) / scale
+
+
+def test_fused_batch_profile_matches_single_steps():
+    from paper_1004_5058_amd import lb
+    specs = []
+    for k, (nx, ny) in enumerate([(512, 256), (300, 77), (1024, 130)]):
+        ra, rb = inputs.emulsion(nx, ny, seed=50 + k)
+        u = 0.01 * (k + 1)
+        specs.append(dict(nx=nx, ny=ny, rho_a=ra, rho_b=rb, ux=None, uy=None, u_top=u, u_bot=-u))
+    res = []
+    for per_pass in (1, 2):
+        b = lb.Batch(specs, storage="f32", profile=True)
+        b.set_fusion(per_pass, 64)
+        b.step(26)
+        res.append(([b.fields(k) for k in range(len(specs))], b.stress(),
+                    [b.profile(k)[0] for k in range(len(specs))]))
+        b.close()
+    for a, c in zip(res[0][0], res[1][0]):
+        for x, y in zip(a, c):
+            np.testing.assert_array_equal(y, x)
+    for x, y in zip(res[0][1][:2], res[1][1][:2]):
+        np.testing.assert_array_equal(y, x)
+    for q1, q2 in zip(res[0][2], res[1][2]):
+        assert np.max(np.abs(q2 - q1)) <= 1e-13 * np.max(np.abs(q1))
