@@ -181,7 +181,8 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
  * steps; the line profile (lb_profile), when on, is accumulated too, from
  * partial sums grouped by the fused kernel's tiles, so it agrees with single
  * steps to FP64 rounding.  Tiles of 250 columns x ly2 rows (ly2 = 0: the
- * smallest height that leaves at most one tile per compute unit).  LB_EINVAL
+ * height whose tiles, handed out greedily to the compute units at h + 8 ticks
+ * per tile of h rows, finish first).  LB_EINVAL
  * unless the storage is LB_F32 and the device grants the kernel's shared
  * memory (about 125 KiB per block). */
 lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <queue>
 #include <vector>
 
 #include "../../include/lb.h"
@@ -268,6 +269,57 @@ void drop_graphs(lbb_handle* h)
         if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
 }
 
+// Makespan, in ticks, of the fused tiles of height ly2 listed lattice by
+// lattice and scheduled greedily on ncu compute units.
+long long fused_makespan(const lbb_handle* h, int ly2, int ncu)
+{
+    std::priority_queue<long long, std::vector<long long>, std::greater<long long>> free_at;
+    for (int c = 0; c < ncu; ++c) free_at.push(0);
+    long long end = 0;
+    for (const Lat& a : h->lats) {
+        const int strips = (a.p.nx + lbk::TW2 - 1) / lbk::TW2;
+        const int lh = std::min(ly2, a.p.ny);
+        for (int st = 0; st < strips; ++st)
+            for (int y = 0; y < a.p.ny; y += lh) {
+                const long long t = free_at.top() + std::min(lh, a.p.ny - y) + 8;
+                free_at.pop();
+                free_at.push(t);
+                end = std::max(end, t);
+            }
+    }
+    return end;
+}
+
+// Automatic fused tile height: the candidate with the smallest makespan (ties:
+// the taller tiles, fewer of them).  Candidates: fixed heights and, for each
+// number of rounds r = 1..4, the smallest height whose tiles fit r rounds.
+int auto_ly2(const lbb_handle* h)
+{
+    int dev = 0, ncu = 256, maxny = 1;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        ncu = prop.multiProcessorCount;
+    for (const Lat& a : h->lats) maxny = std::max(maxny, a.p.ny);
+    std::vector<int> cand = {16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512};
+    for (int r = 1; r <= 4; ++r) {
+        for (int l2 = 16; l2 < maxny; ++l2) {
+            long long it = 0;
+            for (const Lat& a : h->lats)
+                it += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * ((a.p.ny + l2 - 1) / l2);
+            if (it <= (long long)r * ncu) { cand.push_back(l2); break; }
+        }
+    }
+    cand.push_back(maxny);
+    int best = maxny;
+    long long best_t = -1;
+    for (int c : cand) {
+        if (c < 1 || c > maxny) continue;
+        const long long t = fused_makespan(h, c, ncu);
+        if (best_t < 0 || t < best_t || (t == best_t && c > best)) { best_t = t; best = c; }
+    }
+    return best;
+}
+
 // Work decomposition for launch shape (bx, ly): tiles per lattice, each
 // lattice's first item rounded up to a multiple of 8 (one tile per XCD slot),
 // and the item -> lattice table the step kernel reads (-1: padding).
@@ -294,27 +346,12 @@ lb_status decompose(lbb_handle* h)
     }
     if (item > h->lay.max_items) return fail(LB_EINVAL, "launch shape gives more work items than planned");
     h->ntot = item;
-    // Fused two-step tiles: TW2 columns x ly2 rows.  ly2 = 0 picks the
-    // smallest height that leaves at most one tile per compute unit.
+    // Fused two-step tiles: TW2 columns x ly2 rows.  ly2 = 0 picks the height
+    // whose tiles, handed to the compute units in table order (each takes the
+    // next tile when it finishes one), finish first; a tile of h rows costs
+    // h + 8 ticks (the overlap rows of the two steps), whatever its width.
     int ly2 = h->ly2;
-    if (ly2 <= 0) {
-        int dev = 0, ncu = 256, maxny = 1;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            ncu = prop.multiProcessorCount;
-        long long rows = 0;
-        for (const Lat& a : h->lats) {
-            rows += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * a.p.ny;
-            maxny = std::max(maxny, a.p.ny);
-        }
-        ly2 = (int)std::max<long long>(16, (rows + ncu - 1) / ncu);
-        for (; ly2 < maxny; ++ly2) {
-            long long it = 0;
-            for (const Lat& a : h->lats)
-                it += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * ((a.p.ny + ly2 - 1) / ly2);
-            if (it <= ncu) break;
-        }
-    }
+    if (ly2 <= 0) ly2 = auto_ly2(h);
     int item2 = 0;
     h->tiles2.clear();
     for (size_t k = 0; k < h->lats.size(); ++k) {
