@@ -94,10 +94,15 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
     lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=variant_storage(variant), profile=False,
                      **inputs.COUPLINGS)
     del ra, rb, ux, uy
-    shape = lat.autotune(tune_cache, steps=10) if tune_cache is not None else None
+    if tune_cache is not None:
+        lat.autotune(tune_cache, steps=10)
     if variant_storage(variant) == "f32":
         # the tuner may pick either; each variant states its own steps per pass
-        lat.set_fusion(STEPS_PER_LAUNCH.get(variant, 1))
+        # (a tuned fused tile height is kept)
+        want = STEPS_PER_LAUNCH.get(variant, 1)
+        if lat.launch()["steps_per_pass"] != want:
+            lat.set_fusion(want)
+    shape = lat.launch()
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -113,20 +118,7 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
     lups = float(n) * n
     return dict(ms_per_step=1e3 * wall / steps, mlups=lups * steps / wall / 1e6,
                 ms_kernel=ms_kernel, stress=[sb, st], nsamples=ns,
-                shape=None if shape is None else {"bx": shape[0], "ly": shape[1]})
-
-
-def _batch_passes(tune_cache, storage, n, sites):
-    """Steps per pass and fused tile height the tuning cache holds for a batch
-    (keys end in <storage>/batch<n>_<sites>)."""
-    try:
-        with open(tune_cache) as f:
-            entries = json.load(f)
-    except (TypeError, OSError, ValueError):
-        return {}
-    suffix = f"/{storage}/batch{n}_{sites}"
-    e = next((v for k, v in entries.items() if k.endswith(suffix)), {})
-    return {"steps_per_pass": e.get("fusion", 1), "ly2": e.get("ly2", 0)} if e else {}
+                shape=shape)
 
 
 def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
@@ -142,25 +134,23 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     draws = inputs.ensemble(n_lat, seed=seed)
     specs = flowcurve.lattice_specs(draws, inputs.COUPLINGS)
     sites = sum(s["nx"] * s["ny"] for s in specs)
+    b = lb.Batch(specs, storage="f32", profile=True)
     if tune_cache is not None:
         # tuned before the timed run; the run applies the cached entry
-        b = lb.Batch(specs, storage="f32", profile=True)
-        tuned = b.autotune(tune_cache, steps=3)
-        b.close()
-    else:
-        tuned = (0, 0, 0, 0.0)
+        b.autotune(tune_cache, steps=3)
+    shape = b.launch()
+    b.close()
     rows_b, wall_b = flowcurve.run_batched(specs, steps, tune_cache=tune_cache)
     print(f"# flow curve: batched {n_lat} lattices x {steps} steps in {wall_b:.2f} s", file=sys.stderr, flush=True)
     rows_p, wall_p = flowcurve.run_plain(specs, steps, tune_cache=tune_cache)
     print(f"# flow curve: plain loop in {wall_p:.2f} s", file=sys.stderr, flush=True)
     agree = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_b, rows_p))
     # the same ensemble in the moment form (tau = 1), batched, tuned shape
+    b = lb.Batch(specs, storage="mom32", profile=True)
     if tune_cache is not None:
-        b = lb.Batch(specs, storage="mom32", profile=True)
-        tm = b.autotune(tune_cache, steps=3)
-        b.close()
-    else:
-        tm = (0, 0, 0, 0.0)
+        b.autotune(tune_cache, steps=3)
+    tm = b.launch()
+    b.close()
     rows_m, wall_m = flowcurve.run_batched(specs, steps, storage="mom32", tune_cache=tune_cache)
     print(f"# flow curve: batched moment form in {wall_m:.2f} s", file=sys.stderr, flush=True)
     agree_m = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_m, rows_b))
@@ -168,15 +158,13 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
                 batched_mom_points_per_hour=round(n_lat * 3600.0 / wall_m, 1), batched_mom_s=round(wall_m, 3),
                 batched_mom_mlups=round(sites * steps / wall_m / 1e6, 1),
                 mom_vs_f32_max_sigma_rel=float(f"{agree_m:.3e}"),
-                mom_launch_shape={"bx": tm[0], "ly": tm[1], "grid": tm[2]},
+                mom_launch_shape={k: tm[k] for k in ("bx", "ly", "grid")},
                 batched_points_per_hour=round(n_lat * 3600.0 / wall_b, 1),
                 plain_points_per_hour=round(n_lat * 3600.0 / wall_p, 1),
                 batched_s=round(wall_b, 3), plain_s=round(wall_p, 3),
                 batched_mlups=round(sites * steps / wall_b / 1e6, 1),
                 plain_mlups=round(sites * steps / wall_p / 1e6, 1),
-                speedup=round(wall_p / wall_b, 3), max_sigma_mismatch=agree,
-                launch_shape=dict({"bx": tuned[0], "ly": tuned[1], "grid": tuned[2]},
-                                  **_batch_passes(tune_cache, "f32", n_lat, sites)))
+                speedup=round(wall_p / wall_b, 3), max_sigma_mismatch=agree, launch_shape=shape)
 
 
 def surrogate_rates(n_train=512, n_cases=10, storage="f32", plain=True):

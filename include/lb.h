@@ -187,6 +187,13 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
  * memory (about 125 KiB per block). */
 lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
 
+/* The launch configuration in effect (as lb_set_launch / lb_set_fusion /
+ * lb_autotune left it): tile width bx and height ly of the single-step
+ * kernel, time steps per pass, and the fused tiles' height with the automatic
+ * choice resolved (reported whatever the steps per pass).  Any pointer may be
+ * NULL.  Host only, never fails on a valid handle. */
+lb_status lb_get_launch(lb_handle* h, int32_t* bx, int32_t* ly, int32_t* steps_per_pass, int32_t* ly2);
+
 /* Checkpoint: the populations in their storage format, the step count and
  * the FP64 stress/profile accumulators.  lb_save with buf = NULL reports the
  * size in *bytes.  Both synchronise.  lb_load requires a handle of the same
@@ -259,6 +266,9 @@ lb_status lb_time_steps(lb_handle* h, int32_t nsteps, double* ms_per_step);
 lb_status lbb_time_steps(lbb_handle* h, int32_t nsteps, double* ms_per_step);
 /* lb_set_fusion for a batch. */
 lb_status lbb_set_fusion(lbb_handle* h, int32_t steps_per_pass, int32_t ly2);
+/* lb_get_launch for a batch, with its persistent grid (0: one block per tile). */
+lb_status lbb_get_launch(lbb_handle* h, int32_t* bx, int32_t* ly, int32_t* grid, int32_t* steps_per_pass,
+                         int32_t* ly2);
 
 #ifdef __cplusplus
 }

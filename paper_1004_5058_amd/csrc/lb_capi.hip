@@ -239,7 +239,8 @@ struct lbb_handle {
     int ly_max = 1;                  // largest rows-per-tile over the lattices
     int graph_steps = 32;
     int fusion = 1;                  // time steps per step-kernel pass: 1, or 2 (k_step2)
-    int ly2 = 0;                     // rows per fused tile (0: about one tile per compute unit)
+    int ly2 = 0;                     // rows per fused tile as set (0: automatic)
+    int ly2_eff = 0;                 // rows per fused tile in effect (the automatic choice resolved)
     int ntot2 = 0;
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // graph starting from buffer 0 / 1
     int watchdog = 0;
@@ -352,6 +353,7 @@ lb_status decompose(lbb_handle* h)
     // h + 8 ticks (the overlap rows of the two steps), whatever its width.
     int ly2 = h->ly2;
     if (ly2 <= 0) ly2 = auto_ly2(h);
+    h->ly2_eff = ly2;
     int item2 = 0;
     h->tiles2.clear();
     for (size_t k = 0; k < h->lats.size(); ++k) {
@@ -1189,6 +1191,12 @@ lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2)
     return set_fusion(&h->b, steps_per_pass, ly2);
 }
 
+lb_status lb_get_launch(lb_handle* h, int32_t* bx, int32_t* ly, int32_t* steps_per_pass, int32_t* ly2)
+{
+    CHECK_H(h);
+    return lbb_get_launch(&h->b, bx, ly, nullptr, steps_per_pass, ly2);
+}
+
 lb_status lb_set_graph(lb_handle* h, int32_t k)
 {
     CHECK_H(h);
@@ -1368,6 +1376,18 @@ lb_status lbb_set_fusion(lbb_handle* h, int32_t steps_per_pass, int32_t ly2)
 {
     CHECK_H(h);
     return set_fusion(h, steps_per_pass, ly2);
+}
+
+lb_status lbb_get_launch(lbb_handle* h, int32_t* bx, int32_t* ly, int32_t* grid, int32_t* steps_per_pass,
+                         int32_t* ly2)
+{
+    CHECK_H(h);
+    if (bx) *bx = h->bx;
+    if (ly) *ly = h->ly;
+    if (grid) *grid = h->grid;
+    if (steps_per_pass) *steps_per_pass = h->fusion;
+    if (ly2) *ly2 = h->ly2_eff;
+    return LB_OK;
 }
 
 lb_status lbb_set_graph(lbb_handle* h, int32_t k)

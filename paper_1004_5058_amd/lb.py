@@ -68,6 +68,8 @@ def load_library(path=LIB_PATH):
         "lb_step": [H, ctypes.c_int32],
         "lb_set_fusion": [H, ctypes.c_int32, ctypes.c_int32],
         "lbb_set_fusion": [H, ctypes.c_int32, ctypes.c_int32],
+        "lb_get_launch": [H] + [ctypes.POINTER(ctypes.c_int32)] * 4,
+        "lbb_get_launch": [H] + [ctypes.POINTER(ctypes.c_int32)] * 5,
         "lb_fields": [H, _DP, _DP, _DP, _DP],
         "lb_fields_device": [H, _VP, _VP, _VP, _VP],
         "lb_populations": [H, _DP],
@@ -301,6 +303,13 @@ class Lattice:
         """1 or 2 time steps per pass of the step kernel (2: FP32 population storage)."""
         _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
+    def launch(self):
+        """The launch configuration in effect: dict(bx, ly, steps_per_pass, ly2),
+        ly2 the fused tile height with the automatic choice resolved."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(_lib.lb_get_launch(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("bx", "ly", "steps_per_pass", "ly2"), (x.value for x in v)))
+
     def autotune(self, cache_path=None, steps=20):
         """Pick the fastest launch shape, and for FP32 the steps per pass (state
         preserved); returns (bx, ly, ms per step)."""
@@ -422,6 +431,13 @@ class Batch:
     def set_fusion(self, steps_per_pass, ly2=0):
         """1 or 2 time steps per pass of the step kernel (2: FP32 population storage)."""
         _check(_lib.lbb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
+
+    def launch(self):
+        """The launch configuration in effect: dict(bx, ly, grid, steps_per_pass,
+        ly2), ly2 the fused tile height with the automatic choice resolved."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(_lib.lbb_get_launch(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("bx", "ly", "grid", "steps_per_pass", "ly2"), (x.value for x in v)))
 
     def time_steps(self, n):
         ms = ctypes.c_double()

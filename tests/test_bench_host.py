@@ -44,18 +44,3 @@ def test_committed_counters_match_the_committed_kernels():
 def test_algorithmic_bytes_per_update(storage, b):
     assert bench.BYTES_PER_LUP[storage] == b
 
-
-def test_batch_passes_read_from_the_tuning_cache(tmp_path):
-    """The flow-curve leg reports the steps per pass and fused tile height the
-    tuning cache holds for its batch (entries without them mean one step per
-    pass; a missing cache or entry reports nothing)."""
-    import bench
-    cache = tmp_path / "t.json"
-    cache.write_text(json.dumps({
-        "gfx950/f32/batch48_45318144": {"bx": 512, "ly": 64, "grid": 0, "fusion": 2, "ly2": 128, "ms": 1.2},
-        "gfx950/mom32/batch48_45318144": {"bx": 128, "ly": 32, "grid": 0, "ms": 0.9}}))
-    assert bench._batch_passes(str(cache), "f32", 48, 45318144) == {"steps_per_pass": 2, "ly2": 128}
-    assert bench._batch_passes(str(cache), "mom32", 48, 45318144) == {"steps_per_pass": 1, "ly2": 0}
-    assert bench._batch_passes(str(cache), "f32", 47, 45318144) == {}
-    assert bench._batch_passes(str(tmp_path / "missing.json"), "f32", 48, 45318144) == {}
-    assert bench._batch_passes(None, "f32", 48, 45318144) == {}

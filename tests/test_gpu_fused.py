@@ -134,6 +134,10 @@ def test_autotune_considers_two_steps_per_pass(tmp_path):
     assert lat.stress() == ref.stress()
     (key, ent), = json.load(open(cache)).items()
     assert ent["fusion"] in (1, 2) and "ly2" in ent and (ent["bx"], ent["ly"]) == (bx, ly)
+    c = lat.launch()
+    assert (c["bx"], c["ly"], c["steps_per_pass"]) == (bx, ly, ent["fusion"])
+    if ent["ly2"]:
+        assert c["ly2"] == ent["ly2"]
     print(f"\n{key}: {ent}")
     prof = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32", profile=True)
     assert prof.autotune(cache, steps=4)[:2] == (bx, ly)
@@ -191,3 +195,26 @@ def test_fused_batch_profile_matches_single_steps():
         np.testing.assert_array_equal(y, x)
     for q1, q2 in zip(res[0][2], res[1][2]):
         assert np.max(np.abs(q2 - q1)) <= 1e-13 * np.max(np.abs(q1))
+
+
+def test_launch_reports_the_configuration_in_effect():
+    """lb_get_launch / lbb_get_launch report what set_launch, set_fusion and a
+    cached autotune entry left in effect, the automatic fused height resolved."""
+    from paper_1004_5058_amd import lb
+    ra, rb = inputs.emulsion(600, 300, seed=2)
+    lat = gpu_lattice(600, 300, ra, rb, u_top=0.01, u_bot=-0.01, storage="f32")
+    lat.set_launch(128, 32)
+    c = lat.launch()
+    assert (c["bx"], c["ly"], c["steps_per_pass"]) == (128, 32, 1) and 1 <= c["ly2"] <= 300
+    lat.set_fusion(2, 40)
+    assert lat.launch() == dict(bx=128, ly=32, steps_per_pass=2, ly2=40)
+    lat.set_fusion(2, 0)
+    c = lat.launch()
+    assert c["steps_per_pass"] == 2 and 1 <= c["ly2"] <= 300
+    lat.close()
+    specs = [dict(nx=300, ny=77, rho_a=ra[:77, :300].copy(), rho_b=rb[:77, :300].copy(), ux=None, uy=None)]
+    b = lb.Batch(specs, storage="f32", profile=True)
+    b.set_launch(256, 16, 512)
+    b.set_fusion(2, 12)
+    assert b.launch() == dict(bx=256, ly=16, grid=512, steps_per_pass=2, ly2=12)
+    b.close()
