@@ -218,3 +218,29 @@ def test_launch_reports_the_configuration_in_effect():
     b.set_fusion(2, 12)
     assert b.launch() == dict(bx=256, ly=16, grid=512, steps_per_pass=2, ly2=12)
     b.close()
+
+
+@pytest.mark.parametrize("resume_per_pass", [2, 1])
+def test_fused_checkpoint_resume(resume_per_pass):
+    """A checkpoint taken with two steps per pass (profile on, so the fused
+    partial sums are part of it) resumes bitwise, whether the resumed run keeps
+    two steps per pass or switches to one: populations, stress and profile
+    equal those of the run that continued without the checkpoint."""
+    nx, ny = 300, 96
+    ra, rb = inputs.emulsion(nx, ny, seed=8)
+    a = gpu_lattice(nx, ny, ra, rb, u_top=0.02, u_bot=-0.02, storage="f32", profile=True)
+    a.set_fusion(2)
+    a.step(30)
+    ck = a.save()
+    a.set_fusion(resume_per_pass)
+    a.step(21)
+    b = gpu_lattice(nx, ny, ra, rb, u_top=0.02, u_bot=-0.02, storage="f32", profile=True)
+    b.set_fusion(resume_per_pass)
+    b.load(ck)
+    assert b.time() == 30
+    b.step(21)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+    assert a.stress() == b.stress()
+    np.testing.assert_array_equal(a.profile()[0], b.profile()[0])
+    a.close()
+    b.close()

@@ -44,7 +44,8 @@ def test_every_replay_matches_direct_launches(storage, per_pass):
         lat.close()
 
 
-def test_every_batch_replay_matches_direct_launches():
+@pytest.mark.parametrize("per_pass", [1, 2])
+def test_every_batch_replay_matches_direct_launches(per_pass):
     need_gpu()
     from paper_1004_5058_amd import lb
     specs = []
@@ -56,6 +57,7 @@ def test_every_batch_replay_matches_direct_launches():
     batches = []
     for graph in (0, 8):
         b = lb.Batch(specs, storage="f32", profile=True)
+        b.set_fusion(per_pass)
         b.set_graph(graph)
         batches.append(b)
     direct, graphed = batches
