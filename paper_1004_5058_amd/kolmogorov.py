@@ -86,10 +86,12 @@ def lattice_kwargs(L, rho0, U0, couplings=None, rho=1.22):
 
 
 def run(L=512, rho0=0.83, U0=0.1, steps=100000, sample_every=1000, average_from=None, storage="f32",
-        couplings=None, device="cuda:0", init="paper", log=None):
+        couplings=None, device="cuda:0", init="paper", log=None, tune=True):
     """Run the protocol on one lattice.  Returns R(t) samples, the profile
     averaged over [average_from, steps), the stress/shear scatter and its
-    Herschel-Bulkley fit (None when fewer than three flowing points)."""
+    Herschel-Bulkley fit (None when fewer than three flowing points).  With
+    tune, the autotuner picks the launch shape and, for FP32, the steps per
+    pass before the run (the results do not depend on either)."""
     from . import lb
     if average_from is None:
         average_from = steps // 2
@@ -97,6 +99,8 @@ def run(L=512, rho0=0.83, U0=0.1, steps=100000, sample_every=1000, average_from=
     kw = lattice_kwargs(L, rho0, U0, couplings, rho=float(np.mean(ra + rb)))
     F0 = kw["fx_amp"]
     lat = lb.Lattice(L, L, ra, rb, None, None, device=device, storage=storage, profile=True, **kw)
+    if tune:
+        lat.autotune(None, steps=5)
     t0 = time.perf_counter()
     ts, Rs = [], []
     t = 0
