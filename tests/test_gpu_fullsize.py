@@ -239,3 +239,29 @@ def test_largest_accepted_fp32_lattice():
         e_j = np.max(np.abs(gux[gy][:, gxs] * (sa + sb) - oux * (oa + ob))) / (1.1 * CS)
         print(f"{n}^2 {kind} corner: rho {e_rho:.2e}, j {e_j:.2e}")
         assert e_rho < 1e-6 and e_j < 1e-6, (kind, e_rho, e_j)
+
+
+def test_species_swap_symmetry_whole_lattice():
+    """A property of the whole 4096^2 lattice in the headline configuration
+    (FP32, two steps per pass, cached shape): with the symmetric couplings,
+    swapping the species' initial densities swaps every population bit for
+    bit after 20 steps (each species runs the same arithmetic, the sums over
+    species commute); the wall stress, summed species by species, agrees to
+    rounding."""
+    need_gpu()
+    from paper_1004_5058_amd import lb
+    ra, rb = inputs.emulsion(N, N, seed=3)
+    ux, uy = inputs.couette(N, N, U, -U)
+    out = []
+    for a, b in ((ra, rb), (rb, ra)):
+        lat = lb.Lattice(N, N, a, b, ux, uy, u_top=U, u_bot=-U, storage="f32", **inputs.COUPLINGS)
+        lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
+        lat.set_fusion(2)
+        lat.step(20)
+        out.append((lat.populations(), lat.stress()))
+        lat.close()
+    (p, s), (q, t) = out
+    np.testing.assert_array_equal(p[0], q[1])
+    np.testing.assert_array_equal(p[1], q[0])
+    assert s[2] == t[2] == 20
+    assert abs(s[0] - t[0]) <= 1e-6 * abs(s[0]) and abs(s[1] - t[1]) <= 1e-6 * abs(s[1])
