@@ -267,13 +267,17 @@ def test_species_swap_symmetry_whole_lattice():
     assert abs(s[0] - t[0]) <= 1e-6 * abs(s[0]) and abs(s[1] - t[1]) <= 1e-6 * abs(s[1])
 
 
-def test_x_translation_equivariance_whole_lattice():
+@pytest.mark.parametrize("variant", ["f32x2", "f16dev", "bf16dev", "mom32"])
+def test_x_translation_equivariance_whole_lattice(variant):
     """Periodic in x: the input rolled by 137 columns (a shift that lines up
     with no tile width, so every site meets other tile edges and halo columns)
-    gives the rolled populations bit for bit after 20 steps in the headline
-    configuration; the wall stress, summed over columns in another order,
-    agrees to rounding."""
+    gives the rolled populations bit for bit after 20 steps, for every variant
+    the benchmark times in its cached launch configuration (FP32 with two
+    steps per pass, the 16-bit forms with their paired halo columns, the
+    moment form with its overlapping tiles); the wall stress, summed over
+    columns in another order, agrees to rounding."""
     need_gpu()
+    storage = "f32" if variant == "f32x2" else variant
     from paper_1004_5058_amd import lb
     ra, rb = inputs.emulsion(N, N, seed=4)
     ux, uy = inputs.couette(N, N, U, -U)
@@ -283,10 +287,11 @@ def test_x_translation_equivariance_whole_lattice():
         a, b = np.roll(ra, shift, axis=1), np.roll(rb, shift, axis=1)
         # an explicit storage base: the default (the domain mean) is summed in
         # another order for the rolled fields and would differ in its last bit
-        lat = lb.Lattice(N, N, a, b, ux, uy, u_top=U, u_bot=-U, storage="f32", rho_ref_a=0.55,
+        lat = lb.Lattice(N, N, a, b, ux, uy, u_top=U, u_bot=-U, storage=storage, rho_ref_a=0.55,
                          rho_ref_b=0.55, **inputs.COUPLINGS)
         lat.autotune(os.path.join(ROOT, "paper_1004_5058_amd", "tuning.json"), steps=5)
-        lat.set_fusion(2)
+        if variant == "f32x2":
+            lat.set_fusion(2)
         lat.step(20)
         out.append((lat.populations(), lat.stress()))
         lat.close()
