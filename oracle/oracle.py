@@ -17,6 +17,16 @@ import numpy as np
 from . import build as _build
 
 _lib = None
+_native = False
+
+
+def use_native_build():
+    """Load the copy built with -march=native for this host (the CPU-baseline
+    timing); same results bit for bit.  Call before the first oracle call."""
+    global _native
+    if _lib is not None and not _native:
+        raise RuntimeError("the oracle library is already loaded")
+    _native = True
 
 
 class _Params(ctypes.Structure):
@@ -61,7 +71,7 @@ class OracleParams:
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build()
+        path = _build.build(native=_native)
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)

@@ -17,6 +17,7 @@
 
 #include "../../include/lb.h"
 #include "lb_device.hpp"
+#include "lb_host.hpp"
 #include "lb_kernels.hpp"
 
 namespace {
@@ -42,27 +43,35 @@ lb_status fail(lb_status code, const char* fmt, ...)
     } while (0)
 
 constexpr size_t ALIGN = 256;
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-size_t storage_size(int storage)
-{
-    switch (storage) {
-    case LB_F64: return 8;
-    case LB_F32: return 4;
-    case LB_F16DEV: return 2;
-    case LB_BF16DEV: return 2;
-    case LB_MOM32: return 4;
-    case LB_MOM64: return 8;
-    default: return 0;
+// Owners that release a HIP event pair or a temporary device buffer on every
+// return path (HIP_TRY returns early).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
-}
+};
+struct TempDeviceBuffer {
+    char* p = nullptr;
+    ~TempDeviceBuffer()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+
+using lbh::align_up;
+using lbh::is_mom;
+using lbh::storage_size;
 
 // Bytes per site of FP64 staging a state buffer must hold (four arrays).
 constexpr size_t STAGE_BYTES_PER_SITE = 4 * sizeof(double);
 
 // Values stored per site: 18 populations, or the 6 moments of the tau = 1 form.
 size_t planes_of(int storage) { return storage >= LB_MOM32 ? 6 : 18; }
-bool is_mom(int storage) { return storage >= LB_MOM32; }
 
 // Two-belt weights on |c|^2 = 1, 2, 4, 5, 8 and D2Q9 belt-1 weights.
 const double P12[5] = {4.0 / 63.0, 4.0 / 135.0, 1.0 / 180.0, 2.0 / 945.0, 1.0 / 15120.0};
@@ -71,28 +80,9 @@ const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0
 
 lb_status validate(const lb_params* p, int storage0)
 {
-    if (!p) return fail(LB_EINVAL, "null parameters");
-    if (p->nx < 1 || p->ny < 2) return fail(LB_EINVAL, "need nx >= 1 and ny >= 2 (got %d x %d)", p->nx, p->ny);
-    if (p->nx > 65536 || p->ny > 65536) return fail(LB_EINVAL, "lattice side above 65536");
-    if (p->storage < 0 || p->storage > 5) return fail(LB_EINVAL, "unknown storage %d", p->storage);
-    if (is_mom(p->storage) && p->tau != 1.0)
-        return fail(LB_EINVAL, "moment storage holds the post-collision state only at tau = 1 (got %g)", p->tau);
-    if (storage0 >= 0 && p->storage != storage0)
-        return fail(LB_EINVAL, "all lattices of a batch share one storage precision");
-    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LB_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
-    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LB_EINVAL, "rho0 must be > 0");
-    const double g[] = {p->g_aa1, p->g_aa2, p->g_bb1, p->g_bb2, p->g_ab, p->u_top, p->u_bot,
-                        p->rho_ref_a, p->rho_ref_b, p->fx_amp, p->fx_k};
-    for (double v : g)
-        if (!std::isfinite(v))
-            return fail(LB_EINVAL, "non-finite coupling, wall speed, reference density or body force");
-    if (p->walls_y != 0 && p->walls_y != 1) return fail(LB_EINVAL, "walls_y must be 0 or 1");
-    // byte offsets inside one species' planes must fit the 32-bit buffer offset
-    const size_t es = storage_size(p->storage);
-    const size_t pitch = align_up((size_t)p->nx, 64);
-    const size_t per = is_mom(p->storage) ? 6 : 9;   // values addressed through one buffer resource
-    if (per * pitch * p->ny * es >= (1ull << 32))
-        return fail(LB_EINVAL, "lattice too large: one buffer resource would exceed 4 GiB");
+    std::string msg;
+    const lb_status st = lbh::validate(p, storage0, &msg);
+    if (st != LB_OK) return fail(st, "%s", msg.c_str());
     return LB_OK;
 }
 
@@ -620,7 +610,8 @@ lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t
                                       hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) { delete h; return fail(LB_EDEVICE, "upload failed: %s", hipGetErrorString(e)); }
     }
-    HIP_TRY(lbk::launch_fill((double*)(h->base + lay.off_res), 8 + 2 * n, 0.0, h->stream));
+    hipError_t ef = lbk::launch_fill((double*)(h->base + lay.off_res), 8 + 2 * n, 0.0, h->stream);
+    if (ef != hipSuccess) { delete h; return fail(LB_EDEVICE, "fill launch failed: %s", hipGetErrorString(ef)); }
     st = reset_acc(h);
     if (st != LB_OK) { delete h; return st; }
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -811,17 +802,15 @@ lb_status steps_direct_warm(lbb_handle* h, int n)
 lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
 {
     if (n < 1 || !ms) return fail(LB_EINVAL, "need n >= 1 and an output");
-    hipEvent_t a, b;
-    HIP_TRY(hipEventCreate(&a));
-    HIP_TRY(hipEventCreate(&b));
-    HIP_TRY(hipEventRecord(a, h->stream));
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventRecord(ev.a, h->stream));
     lb_status st = steps(h, n);
-    HIP_TRY(hipEventRecord(b, h->stream));
-    HIP_TRY(hipEventSynchronize(b));
+    HIP_TRY(hipEventRecord(ev.b, h->stream));
+    HIP_TRY(hipEventSynchronize(ev.b));
     float t = 0;
-    HIP_TRY(hipEventElapsedTime(&t, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
     if (st != LB_OK) return st;
     *ms = (double)t / n;
     return LB_OK;
@@ -835,11 +824,7 @@ lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
 // and restored).  Results are cached in a small JSON file keyed by
 // "<arch>/<storage>/<lattice shape>".
 
-struct TuneEntry {
-    int bx = 0, ly = 0, grid = 0;
-    int fusion = 1, ly2 = 0;   // time steps per pass and fused tile height (0: automatic)
-    double ms = 0;
-};
+using lbh::TuneEntry;
 
 // Whether the handle may run two steps per pass (set_fusion's storage condition).
 bool fusion_allowed(const lbb_handle* h) { return h->storage == LB_F32; }
@@ -875,44 +860,14 @@ std::string tune_key(const lbb_handle* h)
     return buf;
 }
 
-// Reads {"key": {"bx": .., "ly": .., "grid": .., "fusion": .., "ly2": .., "ms": ..}, ...}
-// one entry per line; an entry without "fusion" runs one step per pass.
-std::vector<std::pair<std::string, TuneEntry>> read_cache(const char* path)
-{
-    std::vector<std::pair<std::string, TuneEntry>> out;
-    FILE* f = path ? fopen(path, "r") : nullptr;
-    if (!f) return out;
-    char line[512];
-    while (fgets(line, sizeof line, f)) {
-        const char* q1 = strchr(line, '"');
-        const char* q2 = q1 ? strchr(q1 + 1, '"') : nullptr;
-        if (!q1 || !q2 || !strstr(q2, "{")) continue;
-        TuneEntry e;
-        const char* p;
-        if ((p = strstr(q2, "\"bx\":"))) e.bx = atoi(p + 5);
-        if ((p = strstr(q2, "\"ly\":"))) e.ly = atoi(p + 5);
-        if ((p = strstr(q2, "\"grid\":"))) e.grid = atoi(p + 7);
-        if ((p = strstr(q2, "\"ms\":"))) e.ms = strtod(p + 5, nullptr);
-        if ((p = strstr(q2, "\"fusion\":"))) e.fusion = atoi(p + 9);
-        if ((p = strstr(q2, "\"ly2\":"))) e.ly2 = atoi(p + 6);
-        out.emplace_back(std::string(q1 + 1, q2 - q1 - 1), e);
-    }
-    fclose(f);
-    return out;
-}
-
-lb_status write_cache(const char* path, const std::vector<std::pair<std::string, TuneEntry>>& ents)
+lb_status write_cache(const char* path, const lbh::TuneCache& ents)
 {
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = fopen(tmp.c_str(), "w");
     if (!f) return fail(LB_EINVAL, "cannot write tuning cache %s", path);
-    fprintf(f, "{\n");
-    for (size_t i = 0; i < ents.size(); ++i)
-        fprintf(f, "\"%s\": {\"bx\": %d, \"ly\": %d, \"grid\": %d, \"fusion\": %d, \"ly2\": %d, \"ms\": %.6f}%s\n",
-                ents[i].first.c_str(), ents[i].second.bx, ents[i].second.ly, ents[i].second.grid,
-                ents[i].second.fusion, ents[i].second.ly2, ents[i].second.ms, i + 1 < ents.size() ? "," : "");
-    fprintf(f, "}\n");
-    fclose(f);
+    const std::string text = lbh::format_cache(ents);
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (fclose(f) != 0 || !ok) return fail(LB_EINVAL, "cannot write tuning cache %s", path);
     if (rename(tmp.c_str(), path) != 0) return fail(LB_EINVAL, "cannot replace tuning cache %s", path);
     return LB_OK;
 }
@@ -921,7 +876,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
 {
     if (steps < 1) return fail(LB_EINVAL, "need steps >= 1");
     const std::string key = tune_key(h);
-    auto cache = read_cache(cache_path);
+    auto cache = lbh::read_cache(cache_path);
     for (auto& kv : cache)
         if (kv.first == key && kv.second.bx) {
             lb_status st = set_launch(h, kv.second.bx, kv.second.ly, kv.second.grid);
@@ -941,8 +896,9 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
         ab[k] = a.end - a.off_stress;
         total += fb[k] + ab[k];
     }
-    char* save = nullptr;
-    HIP_TRY(hipMalloc(&save, total));
+    TempDeviceBuffer saved;
+    HIP_TRY(hipMalloc(&saved.p, total));
+    char* const save = saved.p;
     size_t o = 0;
     for (size_t k = 0; k < h->lats.size(); ++k) {
         const Lat& a = h->lats[k];
@@ -1014,7 +970,6 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
         o += fb[k] + ab[k];
     }
     (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(save);
     h->t = t;
     h->nsamples = ns;
     h->graph_steps = gs0;
@@ -1206,14 +1161,16 @@ lb_status lb_set_graph(lb_handle* h, int32_t k)
     return LB_OK;
 }
 
-// Checkpoint format: header, then the current population buffer in its
+// Checkpoint: lbh::CkptHeader, then the current population buffer in its
 // storage format, then the FP64 stress and profile accumulators.
-struct CkptHeader {
-    char magic[8];
-    int32_t version, storage, nx, ny, pitch, profile;
-    int64_t t, nsamples;
-    uint64_t fbytes, sbytes, pbytes;
-};
+lbh::CkptHeader ckpt_header_of(const lbb_handle* b)
+{
+    const Lat& a = b->lats[0];
+    const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
+    const size_t sbb = 2ull * a.p.nx * sizeof(double);
+    const size_t pb = a.p.profile ? prof_entries(a) * sizeof(double) : 0;
+    return lbh::make_header(b->storage, a.p.nx, a.p.ny, a.pitch, a.p.profile, b->t, b->nsamples, fb, sbb, pb);
+}
 
 lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
 {
@@ -1221,31 +1178,18 @@ lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
     if (!bytes) return fail(LB_EINVAL, "null size");
     lbb_handle* b = &h->b;
     const Lat& a = b->lats[0];
-    const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
-    const size_t sbb = 2ull * a.p.nx * sizeof(double);
-    const size_t pb = a.p.profile ? prof_entries(a) * sizeof(double) : 0;
-    const size_t need = sizeof(CkptHeader) + fb + sbb + pb;
+    const lbh::CkptHeader hd = ckpt_header_of(b);
+    const size_t need = sizeof hd + hd.fbytes + hd.sbytes + hd.pbytes;
     if (!buf) { *bytes = need; return LB_OK; }
     if (*bytes < need) return fail(LB_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
-    CkptHeader hd;
-    std::memset(&hd, 0, sizeof hd);
-    std::memcpy(hd.magic, "LBMI355", 8);
-    hd.version = 2;   // 2: planes stored shifted in x by c_ix
-    hd.storage = b->storage;
-    hd.nx = a.p.nx;
-    hd.ny = a.p.ny;
-    hd.pitch = a.pitch;
-    hd.profile = a.p.profile;
-    hd.t = b->t;
-    hd.nsamples = b->nsamples;
-    hd.fbytes = fb;
-    hd.sbytes = sbb;
-    hd.pbytes = pb;
     char* p = (char*)buf;
     std::memcpy(p, &hd, sizeof hd);
-    HIP_TRY(hipMemcpyAsync(p + sizeof hd, b->base + a.off_f[b->cur], fb, hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipMemcpyAsync(p + sizeof hd + fb, b->base + a.off_stress, sbb, hipMemcpyDeviceToHost, b->stream));
-    if (pb) HIP_TRY(hipMemcpyAsync(p + sizeof hd + fb + sbb, b->base + a.off_prof, pb, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(p + sizeof hd, b->base + a.off_f[b->cur], hd.fbytes, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(p + sizeof hd + hd.fbytes, b->base + a.off_stress, hd.sbytes, hipMemcpyDeviceToHost,
+                           b->stream));
+    if (hd.pbytes)
+        HIP_TRY(hipMemcpyAsync(p + sizeof hd + hd.fbytes + hd.sbytes, b->base + a.off_prof, hd.pbytes,
+                               hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     *bytes = need;
     return LB_OK;
@@ -1254,22 +1198,12 @@ lb_status lb_save(lb_handle* h, void* buf, size_t* bytes)
 lb_status lb_load(lb_handle* h, const void* buf, size_t bytes)
 {
     CHECK_H(h);
-    if (!buf || bytes < sizeof(CkptHeader)) return fail(LB_EINVAL, "checkpoint buffer too small");
     lbb_handle* b = &h->b;
     const Lat& a = b->lats[0];
-    CkptHeader hd;
-    std::memcpy(&hd, buf, sizeof hd);
-    if (std::memcmp(hd.magic, "LBMI355", 8) != 0 || hd.version != 2) return fail(LB_ESTATE, "not a checkpoint");
-    if (hd.storage != b->storage || hd.nx != a.p.nx || hd.ny != a.p.ny || hd.pitch != a.pitch ||
-        hd.profile != a.p.profile)
-        return fail(LB_ESTATE, "checkpoint of another lattice shape, storage or profile setting");
-    // the section sizes must be exactly this lattice's (they bound the copies below)
-    const size_t fb = planes_of(b->storage) * a.plane * storage_size(b->storage);
-    const size_t sbb = 2ull * a.p.nx * sizeof(double);
-    const size_t pb = a.p.profile ? prof_entries(a) * sizeof(double) : 0;
-    if (hd.fbytes != fb || hd.sbytes != sbb || hd.pbytes != pb)
-        return fail(LB_ESTATE, "checkpoint section sizes do not match this lattice");
-    if (bytes < sizeof hd + hd.fbytes + hd.sbytes + hd.pbytes) return fail(LB_EINVAL, "truncated checkpoint");
+    lbh::CkptHeader hd;
+    std::string msg;
+    const lb_status st = lbh::check_checkpoint(buf, bytes, ckpt_header_of(b), &hd, &msg);
+    if (st != LB_OK) return fail(st, "%s", msg.c_str());
     const char* p = (const char*)buf;
     b->cur = 0;
     HIP_TRY(hipMemcpyAsync(b->base + a.off_f[0], p + sizeof hd, hd.fbytes, hipMemcpyHostToDevice, b->stream));
@@ -1415,17 +1349,15 @@ lb_status lb_copy_peak(void* dst, const void* src, size_t bytes, void* hip_strea
     const long long n16 = (long long)(bytes / 16);
     const int blocks = (int)std::min<long long>((n16 + 255) / 256, 0x7fffffffLL);
     HIP_TRY(lbk::launch_copy(src, dst, n16, blocks, s));   // warm-up
-    hipEvent_t a, b;
-    HIP_TRY(hipEventCreate(&a));
-    HIP_TRY(hipEventCreate(&b));
-    HIP_TRY(hipEventRecord(a, s));
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventRecord(ev.a, s));
     for (int r = 0; r < reps; ++r) HIP_TRY(lbk::launch_copy(src, dst, n16, blocks, s));
-    HIP_TRY(hipEventRecord(b, s));
-    HIP_TRY(hipEventSynchronize(b));
+    HIP_TRY(hipEventRecord(ev.b, s));
+    HIP_TRY(hipEventSynchronize(ev.b));
     float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
     *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return LB_OK;
 }

@@ -111,6 +111,44 @@ def test_equilibrium_moments(rho, ux, uy):
     assert np.allclose(O.equilibrium(rho, 0, 0), rho * w, rtol=0, atol=1e-16)
 
 
+@pytest.mark.parametrize("with_u", ["both", "x_only", "y_only", "none"])
+def test_init_is_the_local_equilibrium_of_the_given_fields(with_u):
+    """Initial populations (reading: the local equilibrium of the initial
+    densities and velocity, definition under Eq. (1)).  Per species and site
+    the moments of orc_init's output are taken here from the pinned D2Q9
+    tables: sum_i f_is = rho_s, sum_i f_is c_i = rho_s u and
+    sum_i f_is c_ia c_ib = rho_s (c_S^2 delta_ab + u_a u_b), with u_x != u_y,
+    both non-uniform, so a swapped, dropped or mis-signed velocity component
+    fails; the oracle's own field read returns the inputs."""
+    nx, ny = 11, 7
+    ra, rb = inputs.noise(nx, ny, seed=4, mean=0.7, amp=0.3)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    ux = 0.04 * np.sin(0.7 * X + 0.3) + 0.01 * Y / ny
+    uy = -0.03 * np.cos(0.5 * Y - 0.2 * X) + 0.02
+    if with_u in ("y_only", "none"):
+        ux = None
+    if with_u in ("x_only", "none"):
+        uy = None
+    p = C1(nx, ny, walls=True)
+    f = O.init(p, ra, rb, ux, uy)
+    cx, cy, _, _ = O.tables()
+    u = np.zeros((ny, nx)) if ux is None else ux
+    v = np.zeros((ny, nx)) if uy is None else uy
+    for s, rho in enumerate((ra, rb)):
+        fs = f[s]
+        np.testing.assert_allclose(fs.sum(0), rho, rtol=1e-15, atol=0)
+        np.testing.assert_allclose(np.einsum("iyx,i->yx", fs, cx), rho * u, rtol=0, atol=2e-16)
+        np.testing.assert_allclose(np.einsum("iyx,i->yx", fs, cy), rho * v, rtol=0, atol=2e-16)
+        np.testing.assert_allclose(np.einsum("iyx,i->yx", fs, cx * cx), rho * (1 / 3 + u * u), rtol=1e-14)
+        np.testing.assert_allclose(np.einsum("iyx,i->yx", fs, cy * cy), rho * (1 / 3 + v * v), rtol=1e-14)
+        np.testing.assert_allclose(np.einsum("iyx,i->yx", fs, cx * cy), rho * u * v, rtol=0, atol=2e-16)
+    oa, ob, oux, ouy = O.fields(p, f)
+    np.testing.assert_allclose(oa, ra, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(ob, rb, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(oux, u, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ouy, v, rtol=0, atol=1e-15)
+
+
 def test_psi_properties():
     """psi(rho) = rho0 (1 - e^{-rho/rho0}): psi(0) = 0, slope 1 at the origin,
     saturation at rho0, psi(rho0 ln 2) = rho0/2."""
