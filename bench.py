@@ -47,18 +47,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per 2-species lattice update: 18 population loads and
-# 18 stores in the storage format (the moment form: 6 + 6 moments).  "f32x2"
-# is FP32 storage run two steps per pass (lb_set_fusion); its roofline figure
-# keeps the per-update 144 B, while each population actually crosses HBM once
-# per two updates (FLOOR_PER_LUP).
-BYTES_PER_LUP = {"f64": 288, "f32": 144, "f32x2": 144, "f16dev": 72, "bf16dev": 72, "mom32": 48, "mom64": 96}
-FLOOR_PER_LUP = {"f32x2": 72}
-STEPS_PER_LAUNCH = {"f32x2": 2}
+
+# Variants timed on the 4096^2 workload: storage, time steps per kernel pass,
+# the per-update bytes of one step per pass in that storage (18 population
+# loads + 18 stores; the moment form 6 + 6 moments) and the HBM bytes an
+# update must move in the variant as run (two steps per pass: each population
+# is read and written once per two updates, so half).  The roofline object
+# uses the latter: the bytes the kernel cannot avoid, per launch, over the
+# launch's duration.
+VARIANTS = {
+    "f32x2": dict(storage="f32", per_pass=2, bytes_per_lup=144, floor_per_lup=72),
+    "f32": dict(storage="f32", per_pass=1, bytes_per_lup=144, floor_per_lup=144),
+    "f16x2": dict(storage="f16dev", per_pass=2, bytes_per_lup=72, floor_per_lup=36),
+    "bf16x2": dict(storage="bf16dev", per_pass=2, bytes_per_lup=72, floor_per_lup=36),
+    "f16dev": dict(storage="f16dev", per_pass=1, bytes_per_lup=72, floor_per_lup=72),
+    "bf16dev": dict(storage="bf16dev", per_pass=1, bytes_per_lup=72, floor_per_lup=72),
+    "mom32": dict(storage="mom32", per_pass=1, bytes_per_lup=48, floor_per_lup=48),
+}
+DEFAULT_VARIANTS = "f32x2,f32,f16x2,bf16x2,f16dev,bf16dev,mom32"
+# Before each variant's W warm-up steps the same step kernel runs for this
+# long on a separate lattice of the same size and storage: the GPU lowers its
+# clocks while the host sets a lattice up (about a second per 4096^2 lattice),
+# and the first 10-40 launches after that run 3-8 % slower than the steady
+# state (a streaming copy as the warm-up recovers only part of it).  The
+# benchmarked lattice itself takes exactly W untimed and K timed steps.
+CLOCK_RAMP_S = 0.5
 
 
 def variant_storage(v):
-    return "f32" if v == "f32x2" else v
+    return VARIANTS[v]["storage"]
 
 
 def kernel_source_hash():
@@ -69,10 +86,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage):
-    """HBM bytes per kernel launch (a launch advances STEPS_PER_LAUNCH steps)
-    from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source; else None."""
+def measured_traffic(workload, variant):
+    """HBM bytes per kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -80,29 +96,69 @@ def measured_traffic(workload, storage):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    e = d.get(f"{workload}/{storage}")
+    e = d.get(f"{workload}/{variant}")
     if not e or e.get("kernel_hash") != kernel_source_hash():
         return None
-    return e.get("bytes_per_launch", e.get("bytes_per_step"))
+    return e.get("bytes_per_launch")
 
 
-def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
+def stated_precision(workload):
+    """Errors of each storage form against the FP64 step at the workload's
+    stated length (5000 steps), from the committed long-run record."""
+    path = os.path.join(ROOT, "profiles", "precision_couette_emulsion_4096x4096_5000steps.json")
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return None
+
+
+def clock_ramp(variant, n, seconds, tune_cache=None, u=0.02):
+    """Runs the variant's step kernel for `seconds` on a separate n x n lattice
+    (uniform densities: cheap to set up; same kernel, launch shape and bytes
+    per step) and discards it.  Returns the steps taken."""
+    import numpy as np
     import torch
     from paper_1004_5058_amd import inputs, lb
+    vd = VARIANTS[variant]
+    ra = np.full((n, n), 0.55)
+    lat = lb.Lattice(n, n, ra, ra, None, None, u_top=u, u_bot=-u, storage=vd["storage"], profile=False,
+                     **inputs.COUPLINGS)
+    try:
+        if tune_cache is not None:
+            lat.autotune(tune_cache, steps=10)
+        if lat.launch()["steps_per_pass"] != vd["per_pass"]:
+            lat.set_fusion(vd["per_pass"])
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            lat.step(64)
+            torch.cuda.synchronize()
+            done += 64
+        return done
+    finally:
+        lat.close()
+        del lat
+
+
+def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None, ramp_s=0.0):
+    import torch
+    from paper_1004_5058_amd import inputs, lb
+    vd = VARIANTS[variant]
     ra, rb = inputs.emulsion(n, n, seed=seed)
     ux, uy = inputs.couette(n, n, u, -u)
-    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=variant_storage(variant), profile=False,
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=vd["storage"], profile=False,
                      **inputs.COUPLINGS)
     del ra, rb, ux, uy
     if tune_cache is not None:
         lat.autotune(tune_cache, steps=10)
-    if variant_storage(variant) == "f32":
-        # the tuner may pick either; each variant states its own steps per pass
-        # (a tuned fused tile height is kept)
-        want = STEPS_PER_LAUNCH.get(variant, 1)
-        if lat.launch()["steps_per_pass"] != want:
-            lat.set_fusion(want)
+    # the tuner may pick either; each variant states its own steps per pass
+    # (a tuned fused tile height and width are kept)
+    if lat.launch()["steps_per_pass"] != vd["per_pass"]:
+        lat.set_fusion(vd["per_pass"])
     shape = lat.launch()
+    if vd["per_pass"] == 2:
+        shape["lanes"], shape["columns"] = lat.fusion_tile()
+    ramp_steps = clock_ramp(variant, n, ramp_s, tune_cache=tune_cache) if ramp_s > 0 else 0
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -112,13 +168,47 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sb, st, ns = lat.stress()
+    fields = lat.fields()
     lat.close()
     del lat
     torch.cuda.empty_cache()
     lups = float(n) * n
     return dict(ms_per_step=1e3 * wall / steps, mlups=lups * steps / wall / 1e6,
-                ms_kernel=ms_kernel, stress=[sb, st], nsamples=ns,
-                shape=shape)
+                ms_kernel=ms_kernel, stress=[sb, st], nsamples=ns, shape=shape, fields=fields, ramp_steps=ramp_steps)
+
+
+def errors_vs_f64(run, ref):
+    """Density error relative to the largest density, momentum error on the
+    scale rho c_S, and relative error of the mean wall stress."""
+    import numpy as np
+    ra, rb, ux, uy = ref["fields"]
+    a, b, vx, vy = run["fields"]
+    scale_r = max(ra.max(), rb.max())
+    scale_j = (ra + rb).max() / np.sqrt(3.0)
+    e_rho = max(np.abs(a - ra).max(), np.abs(b - rb).max()) / scale_r
+    e_j = max(np.abs(vx * (a + b) - ux * (ra + rb)).max(), np.abs(vy * (a + b) - uy * (ra + rb)).max()) / scale_j
+    s_ref = 0.5 * (ref["stress"][0] + ref["stress"][1])
+    s = 0.5 * (run["stress"][0] + run["stress"][1])
+    return dict(rho=float(f"{e_rho:.3e}"), j=float(f"{e_j:.3e}"), stress=float(f"{abs(s - s_ref) / abs(s_ref):.3e}"))
+
+
+def gpu_run_f64(n, steps, u=0.02, seed=1):
+    """The FP64 population step over `steps` steps (one step per pass): the
+    reference of the variants' error figures.  Its 4096^2 windows match the
+    oracle to <= 1e-15 (tests/test_gpu_fullsize.py)."""
+    import torch
+    from paper_1004_5058_amd import inputs, lb
+    ra, rb = inputs.emulsion(n, n, seed=seed)
+    ux, uy = inputs.couette(n, n, u, -u)
+    lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage="f64", profile=False, **inputs.COUPLINGS)
+    del ra, rb, ux, uy
+    lat.step(steps)
+    sb, st, _ = lat.stress()
+    fields = lat.fields()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return dict(stress=[sb, st], fields=fields)
 
 
 def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
@@ -154,10 +244,24 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     rows_m, wall_m = flowcurve.run_batched(specs, steps, storage="mom32", tune_cache=tune_cache)
     print(f"# flow curve: batched moment form in {wall_m:.2f} s", file=sys.stderr, flush=True)
     agree_m = max(abs(a["sigma"] - c["sigma"]) / max(abs(c["sigma"]), 1e-300) for a, c in zip(rows_m, rows_b))
-    return dict(lattices=n_lat, steps=steps, sites=sites,
+    # The Herschel-Bulkley flow curve: the same sizes and wall speeds at one
+    # fixed coupling set (the parity workload's, G^r = 8.1), batched
+    fixed = [dict(d, g_aa2=inputs.COUPLINGS["g_aa2"], g_bb2=inputs.COUPLINGS["g_bb2"]) for d in draws]
+    specs_f = flowcurve.lattice_specs(fixed, inputs.COUPLINGS)
+    rows_f, wall_f = flowcurve.run_batched(specs_f, steps, tune_cache=tune_cache)
+    print(f"# flow curve: fixed-coupling batch in {wall_f:.2f} s", file=sys.stderr, flush=True)
+    curve = flowcurve.hb_curve(rows_f)
+    curve.update(couplings=dict(g_a=inputs.COUPLINGS["g_aa1"], g_r=inputs.COUPLINGS["g_aa2"],
+                                g_ab=inputs.COUPLINGS["g_ab"]),
+                 wall_s=round(wall_f, 3),
+                 points_S_sigma=[[float(f"{r['S']:.6e}"), float(f"{r['S_bulk']:.6e}"), float(f"{r['sigma']:.6e}")]
+                                 for r in sorted(rows_f, key=lambda r: r["S"])])
+    return dict(lattices=n_lat, steps=steps, sites=sites, hb_flow_curve=curve,
                 batched_mom_points_per_hour=round(n_lat * 3600.0 / wall_m, 1), batched_mom_s=round(wall_m, 3),
                 batched_mom_mlups=round(sites * steps / wall_m / 1e6, 1),
                 mom_vs_f32_max_sigma_rel=float(f"{agree_m:.3e}"),
+                mom_note="moment-form stresses differ from the FP32 population batch by this much "
+                         "(two FP32 trajectories of chaotic emulsions after 10^4 steps): not the 1 % bar",
                 mom_launch_shape={k: tm[k] for k in ("bx", "ly", "grid")},
                 batched_points_per_hour=round(n_lat * 3600.0 / wall_b, 1),
                 plain_points_per_hour=round(n_lat * 3600.0 / wall_p, 1),
@@ -167,15 +271,16 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
                 speedup=round(wall_p / wall_b, 3), max_sigma_mismatch=agree, launch_shape=shape)
 
 
-def surrogate_rates(n_train=512, n_cases=10, storage="f32", plain=True):
+def surrogate_rates(n_cases=10, k=4, storage="f32", plain=True):
     """Stress-controlled flow-curve points per hour: the shear rate at which a
     fixed-coupling lattice reaches a target wall stress, accepted when a
-    lattice run is within 1 % (a lattice run checks every point).  Three ways:
-    the plain loop (bisection, one lattice run at a time), batched bisection
-    (one launch per step for all open cases), and batched with the surrogate
-    (network trained by the HIP kernels on a batched ensemble; the ensemble
-    and the training are charged to it).  `storage` is the lattice storage of
-    every run (the training ensemble, the targets and the solvers)."""
+    lattice run is within 1 % (every accepted point is a lattice result).  A
+    stream of two batches of cases (A, then B): batched k-section (k lattice
+    runs per case and round, one launch per step for all of them), and batched
+    with the surrogate, whose network the HIP kernels train on batch A's
+    lattice runs (no separate ensemble; the training is charged) and which
+    places batch B's runs.  The plain per-run loop (bisection, one lattice run
+    at a time) serves batch B for reference."""
     from paper_1004_5058_amd import surrogate
     G = surrogate.GAIN
     nx, ny, steps, seed = G["nx"], G["ny"], G["steps"], G["seed"]
@@ -183,41 +288,57 @@ def surrogate_rates(n_train=512, n_cases=10, storage="f32", plain=True):
 
     def lattice(batched):
         return lambda pts: surrogate.lattice_stresses(pts, nx, ny, steps, seed, storage=storage, batched=batched)
-    t0 = time.perf_counter()
-    pts = surrogate.draw_points(n_train, 300, (S_lo, S_hi), G["g1"], G["g2"])
-    sig = lattice(True)(pts)
-    rows = [dict(g_aa1=g1, g_aa2=g2, S=S, sigma=v) for (g1, g2, S), v in zip(pts, sig)]
-    surr = surrogate.FlowSurrogate(max_rows=1024, seed=0)
-    surr.fit(rows, iters=4000, lr=3e-3)
-    t_train = time.perf_counter() - t0
-    cases = surrogate.draw_points(n_cases, 31, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
-    targets = lattice(True)(cases)
-    out = dict(lattice=f"{nx}x{ny}", storage=storage, steps=steps, cases=n_cases, train_lattices=n_train,
-               train_s=round(t_train, 2))
-    legs = ((("plain", "bisect", False),) if plain else ()) + (("batched", "bisect", True),
-                                                              ("batched_surrogate", "surrogate", True))
-    for name, method, batched in legs:
+    cases_a = surrogate.draw_points(n_cases, 31, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
+    cases_b = surrogate.draw_points(n_cases, 47, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
+    targets = lattice(True)(cases_a + cases_b)
+    ta, tb = targets[:n_cases], targets[n_cases:]
+    out = dict(lattice=f"{nx}x{ny}", storage=storage, steps=steps, cases_per_batch=n_cases, runs_per_round=k)
+    r, _, sb_k = surrogate.stream_points(cases_a, ta, cases_b, tb, lattice(True), S_lo, S_hi, k=k)
+    out["batched"] = r
+    print(f"# stress-controlled points ({storage}), batched k-section: {r}", file=sys.stderr, flush=True)
+    surr = surrogate.FlowSurrogate(max_rows=2048, seed=0)
+    r, _, sb_n = surrogate.stream_points(cases_a, ta, cases_b, tb, lattice(True), S_lo, S_hi, k=k,
+                                         use_network=True, surr=surr)
+    # the network's error on batch B's lattice runs (after the fact)
+    import numpy as np
+    err = [abs(float(surr.predict(g1, g2, np.exp(x))[0]) - sig) / abs(sig)
+           for s, (g1, g2, _) in zip(sb_n, cases_b) for x, _, sig in s.points]
+    r["network_rel_err_on_B_runs"] = dict(median=float(f"{np.median(err):.3e}"),
+                                          p90=float(f"{np.quantile(err, 0.9):.3e}"))
+    out["batched_surrogate"] = r
+    print(f"# stress-controlled points ({storage}), batched with the surrogate: {r}", file=sys.stderr, flush=True)
+    if plain:
         t0 = time.perf_counter()
-        solvers, rounds = surrogate.stress_controlled_points(cases, targets, method, lattice(batched), S_lo, S_hi,
-                                                             surr=surr)
+        ss = [surrogate.RootSearch(t, S_lo, S_hi, k=1) for t in tb]
+        for s, (g1, g2, _) in zip(ss, cases_b):
+            surrogate.search_batched([s], lambda todo: lattice(False)([(g1, g2, S) for _, S in todo]))
         wall = time.perf_counter() - t0
-        if method == "surrogate":
-            wall_all = wall + t_train
-        else:
-            wall_all = wall
-        ok = sum(s.result is not None for s in solvers)
-        out[name] = dict(lattice_runs=sum(s.runs for s in solvers), accepted=ok, wall_s=round(wall_all, 2),
-                         points_per_hour=round(ok * 3600.0 / wall_all, 1))
-        if method == "surrogate":
-            out[name]["wall_s_without_training"] = round(wall, 2)
-        print(f"# stress-controlled points ({storage}), {name}: {out[name]}", file=sys.stderr, flush=True)
+        ok = sum(s.result is not None for s in ss)
+        out["plain_batch_B"] = dict(lattice_runs=sum(s.runs for s in ss), accepted=ok, wall_s=round(wall, 2),
+                                    points_per_hour=round(ok * 3600.0 / wall, 1))
+        print(f"# stress-controlled points ({storage}), plain loop on batch B: {out['plain_batch_B']}",
+              file=sys.stderr, flush=True)
     return out
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, steps=7, u=0.02, seed=1):
-    """The FP64 oracle on the same 4096^2 workload, a bounded number of steps."""
+    """The FP64 oracle on the same 4096^2 workload, a bounded number of steps,
+    built -O3 -march=native for this host (no contraction: the same results)."""
     from oracle import oracle as O
     from paper_1004_5058_amd import inputs
+    O.use_native_build()
     ra, rb = inputs.emulsion(n, n, seed=seed)
     ux, uy = inputs.couette(n, n, u, -u)
     p = O.OracleParams(nx=n, ny=n, walls=True, u_top=u, u_bot=-u, **inputs.COUPLINGS)
@@ -226,8 +347,8 @@ def cpu_baseline(n, steps=7, u=0.02, seed=1):
     t0 = time.perf_counter()
     f, _, _ = O.run(p, f, steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=round(float(n) * n * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+    return dict(value=round(float(n) * n * steps / dt / 1e6, 3), unit="MLUPS", cores=O.threads(), kind="oracle",
+                cpu=cpu_model(), build="gcc -O3 -march=native -ffp-contract=off -fopenmp",
                 sample=f"{steps} FP64 oracle steps of the full {n}x{n} lattice ({dt:.1f} s)")
 
 
@@ -236,6 +357,7 @@ import json, sys, time
 sys.path.insert(0, sys.argv[1])
 from oracle import oracle as O
 from paper_1004_5058_amd import inputs
+O.use_native_build()
 n, steps, u = int(sys.argv[2]), int(sys.argv[3]), 0.02
 ra, rb = inputs.emulsion(n, n, seed=1)
 ux, uy = inputs.couette(n, n, u, -u)
@@ -244,7 +366,7 @@ f = O.init(p, ra, rb, ux, uy)
 t0 = time.perf_counter()
 O.run(p, f, steps)
 dt = time.perf_counter() - t0
-print(json.dumps({"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+print(json.dumps({"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.threads(),
                   "sample": f"{steps} FP64 oracle steps of a {n}x{n} lattice of the same recipe ({dt:.1f} s)"}))
 """
 
@@ -266,8 +388,13 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--variants", default="f32x2,f32,f16dev,bf16dev,mom32")
+    ap.add_argument("--variants", default=DEFAULT_VARIANTS,
+                    help="comma-separated, the first is the headline: " + ", ".join(VARIANTS))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ramp", type=float, default=CLOCK_RAMP_S,
+                    help="seconds of the same step kernel on a separate lattice before each variant's warm-up "
+                         "steps (0: none)")
+    ap.add_argument("--no-errors", action="store_true", help="skip the FP64 reference run of the error figures")
     ap.add_argument("--no-flowcurve", action="store_true", help="skip the batched-vs-plain flow-curve leg")
     ap.add_argument("--flow-steps", type=int, default=10000)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the stress-controlled surrogate leg")
@@ -280,10 +407,15 @@ def main():
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: the library drives one GPU per process; --gpus {a.gpus} is not supported "
-              "(sharding by y-slabs with halo rows, or whole lattices per GPU, is not implemented).",
-              file=sys.stderr)
+        print(f"bench.py: every GPU box here has one GPU and the library drives one GPU per process; --gpus {a.gpus} "
+              "is not supported (sharding by y-slabs with halo rows, or whole lattices per GPU, is designed but not "
+              "built).", file=sys.stderr)
         sys.exit(2)
+    variants = [v for v in a.variants.split(",") if v]
+    for v in variants:
+        if v not in VARIANTS:
+            print(f"bench.py: unknown variant {v} (known: {', '.join(VARIANTS)})", file=sys.stderr)
+            sys.exit(2)
     import torch
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
@@ -298,16 +430,25 @@ def main():
         torch.cuda.empty_cache()
     n = a.size
     workload = f"couette_emulsion_{n}x{n}"
-    variants = [v for v in a.variants.split(",") if v]
+    tune = None if a.no_tune else a.tune_cache
     res = {}
     for v in variants:
-        res[v] = gpu_run(v, n, a.steps, a.warmup, tune_cache=None if a.no_tune else a.tune_cache)
+        res[v] = gpu_run(v, n, a.steps, a.warmup, tune_cache=tune, ramp_s=a.ramp)
         print(f"# {v}: {res[v]['mlups']:.0f} MLUPS, kernel {res[v]['ms_kernel']:.4f} ms/step", file=sys.stderr,
               flush=True)
+    ref = None
+    if not a.no_errors:
+        # the FP64 population step over the same number of steps: the
+        # reference of every variant's error figures
+        ref = gpu_run_f64(n, a.steps + a.warmup)
+    torch.cuda.empty_cache()
     head = variants[0]
     r = res[head]
-    bytes_step = BYTES_PER_LUP[head] * float(n) * n
-    achieved = bytes_step / (r["ms_kernel"] * 1e-3) / 1e9
+    vd = VARIANTS[head]
+    lups = float(n) * n
+    ms_launch = r["ms_kernel"] * vd["per_pass"]
+    bytes_launch = vd["floor_per_lup"] * vd["per_pass"] * lups
+    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     traffic = measured_traffic(workload, head)
     line = {
         "metric": "MLUPS (2-species)",
@@ -320,40 +461,50 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": variant_storage(head),
+        "dtype": "f32" if vd["storage"] in ("f32", "mom32") else vd["storage"],
         "data": "synthetic (seeded emulsion start, linear Couette velocity)",
-        "config": {"workload": workload, "nx": n, "ny": n, "storage": variant_storage(head),
-                   "steps_per_pass": STEPS_PER_LAUNCH.get(head, 1), "walls": "bounce-back +-0.02",
+        "config": {"workload": workload, "nx": n, "ny": n, "storage": vd["storage"],
+                   "steps_per_pass": vd["per_pass"], "walls": "bounce-back +-0.02",
                    "tau": 1.0, "rho0": 0.83, "G": [-9.0, 8.1, -9.0, 8.1, 0.405]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
-        "variants": {v: {"mlups": round(res[v]["mlups"], 1), "ms_kernel": round(res[v]["ms_kernel"], 5),
-                         "launch_shape": res[v]["shape"],
-                         "alg_gbs": round(BYTES_PER_LUP[v] * float(n) * n / (res[v]["ms_kernel"] * 1e-3) / 1e9, 1),
-                         "bytes_per_lup": BYTES_PER_LUP[v],
-                         "sigma_bot_top": [float(f"{x:.7e}") for x in res[v]["stress"]]} for v in variants},
+                     "traffic": traffic,
+                     "bytes_per_launch": bytes_launch, "steps_per_launch": vd["per_pass"],
+                     "ms_per_launch": round(ms_launch, 5),
+                     "effective_gbs": round(vd["bytes_per_lup"] * lups / (r["ms_kernel"] * 1e-3) / 1e9, 1)},
+        "variants": {},
+        "clock_ramp": (f"{a.ramp:g} s of the same step kernel on a separate {n}x{n} lattice of the same storage "
+                       f"before the {a.warmup} warm-up steps ({r['ramp_steps']} steps)") if a.ramp > 0 else None,
     }
     for v in variants:
-        line["variants"][v]["frac"] = round(line["variants"][v]["alg_gbs"] / HBM_PEAK_GBS, 4)
-        if v in FLOOR_PER_LUP:
-            fl = FLOOR_PER_LUP[v] * float(n) * n / (res[v]["ms_kernel"] * 1e-3) / 1e9
-            line["variants"][v]["floor_bytes_per_lup"] = FLOOR_PER_LUP[v]
-            line["variants"][v]["floor_gbs"] = round(fl, 1)
-            line["variants"][v]["frac_of_floor"] = round(fl / HBM_PEAK_GBS, 4)
+        d = VARIANTS[v]
+        rv = res[v]
+        fl = d["floor_per_lup"] * lups / (rv["ms_kernel"] * 1e-3) / 1e9
+        line["variants"][v] = {
+            "mlups": round(rv["mlups"], 1), "ms_kernel": round(rv["ms_kernel"], 5), "launch_shape": rv["shape"],
+            "storage": d["storage"], "steps_per_pass": d["per_pass"],
+            "floor_bytes_per_lup": d["floor_per_lup"], "gbs": round(fl, 1), "frac": round(fl / HBM_PEAK_GBS, 4),
+            "bytes_per_lup_one_step": d["bytes_per_lup"],
+            "effective_gbs": round(d["bytes_per_lup"] * lups / (rv["ms_kernel"] * 1e-3) / 1e9, 1),
+            "sigma_bot_top": [float(f"{x:.7e}") for x in rv["stress"]]}
+        if ref is not None:
+            line["variants"][v]["err_vs_f64"] = dict(errors_vs_f64(rv, ref), steps=a.steps + a.warmup)
+    stated = stated_precision(workload)
+    if stated is not None:
+        line["precision_at_5000_steps"] = stated
+    for v in variants:
+        del res[v]["fields"]
     from paper_1004_5058_amd import lb
     cp = lb.copy_peak()
-    per_launch = STEPS_PER_LAUNCH.get(head, 1)
-    measured = None if traffic is None else traffic / (per_launch * r["ms_kernel"] * 1e-3) / 1e9
+    measured = None if traffic is None else traffic / (ms_launch * 1e-3) / 1e9
     line["hbm"] = {"measured_gbs": None if measured is None else round(measured, 1),
                    "measured_frac_of_peak": None if measured is None else round(measured / HBM_PEAK_GBS, 4),
                    "measured_frac_of_copy_peak": None if measured is None else round(measured / cp, 4),
-                   "steps_per_launch": per_launch,
-                   "copy_peak_gbs": round(cp, 1), "frac_of_copy_peak": round(achieved / cp, 4),
+                   "copy_peak_gbs": round(cp, 1), "achieved_frac_of_copy_peak": round(achieved / cp, 4),
                    "copy": "library streaming copy, 16 B per lane, 2 GiB read + 2 GiB written"}
     if not a.no_flowcurve:
         try:
-            line["flowcurve"] = flowcurve_rates(a.flow_steps, tune_cache=None if a.no_tune else a.tune_cache)
+            line["flowcurve"] = flowcurve_rates(a.flow_steps, tune_cache=tune)
             print(f"# flow curve: {line['flowcurve']}", file=sys.stderr, flush=True)
         except Exception as e:  # reported, never hidden
             line["flowcurve"] = {"error": repr(e)}

@@ -180,12 +180,24 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
  * runs alone.  Populations and wall stress are bitwise those of single
  * steps; the line profile (lb_profile), when on, is accumulated too, from
  * partial sums grouped by the fused kernel's tiles, so it agrees with single
- * steps to FP64 rounding.  Tiles of 250 columns x ly2 rows (ly2 = 0: the
- * height whose tiles, handed out greedily to the compute units at h + 8 ticks
- * per tile of h rows, finish first).  LB_EINVAL
- * unless the storage is LB_F32 and the device grants the kernel's shared
- * memory (about 125 KiB per block). */
+ * steps to FP64 rounding.  Tiles of W columns x ly2 rows, W from
+ * lb_set_fusion_tile (ly2 = 0: the height whose tiles, handed out greedily to
+ * the blocks the device runs at once at h + 8 ticks per tile of h rows,
+ * finish first).  LB_EINVAL unless the storage is LB_F32, LB_F16DEV or
+ * LB_BF16DEV (the 16-bit forms: nx even) and the device grants the kernel's
+ * shared memory. */
 lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
+
+/* Block width of the two-steps-per-pass kernel: lanes = 128, 192 or 256
+ * threads per time step (the block has twice as many), or 0 for the width
+ * with the most waves resident per compute unit.  A tile stores lanes - 6
+ * columns (FP32) or lanes - 8 (16-bit): the step-t columns beyond them are the
+ * overlap step t+1 needs.  Results are bitwise independent of the width.
+ * LB_EINVAL for another value. */
+lb_status lb_set_fusion_tile(lb_handle* h, int32_t lanes);
+/* The width in effect (automatic choice resolved) and its stored columns per
+ * tile; either pointer may be NULL. */
+lb_status lb_get_fusion_tile(lb_handle* h, int32_t* lanes, int32_t* columns);
 
 /* The launch configuration in effect (as lb_set_launch / lb_set_fusion /
  * lb_autotune left it): tile width bx and height ly of the single-step
@@ -205,15 +217,17 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
  * {64, 128, 256, 512} as lb_set_launch admits them, ly in {8..256}, shapes
  * within the device's shared memory per block; for batches also persistent grids of 1, 2
  * and 4 blocks per compute unit) on this lattice; where lb_set_fusion admits
- * two steps per pass (FP32), also that mode behind the best shape, at the
- * automatic tile height and at 64, 128 and 256 rows.  Applies the fastest (shape and steps per pass; *ms is its time per
- * step) and restores the simulation state exactly (populations, accumulators,
- * step count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid,
- * fusion, ly2, ms}}, key "<gfx arch>/<storage>/<nx>x<ny>" (batches:
+ * two steps per pass (FP32, 16-bit), also that mode behind the best shape,
+ * for each block width of lb_set_fusion_tile the device grants, at the
+ * automatic tile height and at 64, 128 and 256 rows.  Applies the fastest
+ * (shape, steps per pass and fused width; *ms is its time per step) and
+ * restores the simulation state exactly (populations, accumulators, step
+ * count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid,
+ * fusion, ly2, fw, ms}}, key "<gfx arch>/<storage>/<nx>x<ny>" (batches:
  * "batch<n>_<sites>"); a cached entry is applied without timing (its fusion
- * only where admitted; entries without it mean one step per pass), a new
- * result is added.  Synchronises.  Allocates a temporary device copy of the
- * state while timing. */
+ * only where admitted; entries without it mean one step per pass, without fw
+ * the automatic width), a new result is added.  Synchronises.  Allocates a
+ * temporary device copy of the state while timing. */
 lb_status lb_autotune(lb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
                       double* ms);
 lb_status lbb_autotune(lbb_handle* h, const char* cache_path, int32_t steps, int32_t* bx, int32_t* ly,
@@ -264,8 +278,10 @@ lb_status lbb_destroy(lbb_handle* h);
  * synchronises.  Used by the benchmark for the roofline figure. */
 lb_status lb_time_steps(lb_handle* h, int32_t nsteps, double* ms_per_step);
 lb_status lbb_time_steps(lbb_handle* h, int32_t nsteps, double* ms_per_step);
-/* lb_set_fusion for a batch. */
+/* lb_set_fusion, lb_set_fusion_tile and lb_get_fusion_tile for a batch. */
 lb_status lbb_set_fusion(lbb_handle* h, int32_t steps_per_pass, int32_t ly2);
+lb_status lbb_set_fusion_tile(lbb_handle* h, int32_t lanes);
+lb_status lbb_get_fusion_tile(lbb_handle* h, int32_t* lanes, int32_t* columns);
 /* lb_get_launch for a batch, with its persistent grid (0: one block per tile). */
 lb_status lbb_get_launch(lbb_handle* h, int32_t* bx, int32_t* ly, int32_t* grid, int32_t* steps_per_pass,
                          int32_t* ly2);

@@ -47,6 +47,7 @@
  *             5 (1,1); 6 (-1,1); 7 (-1,-1); 8 (1,-1).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -376,4 +377,10 @@ void orc_sums(const orc_params* p, const double* f, double* out4)
     out4[1] = m[1];
     out4[2] = jx;
     out4[3] = jy;
+}
+
+/* Threads the parallel loops above run on (reported beside the oracle's timing). */
+int orc_threads(void)
+{
+    return omp_get_max_threads();
 }

@@ -89,6 +89,8 @@ def lib():
         L.orc_step.argtypes = [pp, dp, dp, dp]
         L.orc_run.argtypes = [pp, dp, ctypes.c_int, dp]
         L.orc_sums.argtypes = [pp, dp, dp]
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -196,3 +198,8 @@ def sums(p: OracleParams, f):
     cp = p._c()
     lib().orc_sums(ctypes.byref(cp), _ptr(f), _ptr(out))
     return out  # mass_A, mass_B, jx, jy
+
+
+def threads():
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().orc_threads())

@@ -72,6 +72,8 @@ constexpr size_t STAGE_BYTES_PER_SITE = 4 * sizeof(double);
 
 // Values stored per site: 18 populations, or the 6 moments of the tau = 1 form.
 size_t planes_of(int storage) { return storage >= LB_MOM32 ? 6 : 18; }
+// Storages with a fused two-steps-per-pass kernel: FP32 and the 16-bit forms.
+bool fusion_storage(int storage) { return storage == LB_F32 || storage == LB_F16DEV || storage == LB_BF16DEV; }
 
 // Two-belt weights on |c|^2 = 1, 2, 4, 5, 8 and D2Q9 belt-1 weights.
 const double P12[5] = {4.0 / 63.0, 4.0 / 135.0, 1.0 / 180.0, 2.0 / 945.0, 1.0 / 15120.0};
@@ -119,9 +121,13 @@ Layout plan(std::vector<Lat>& lats)
     long long items = 0;
     for (const auto& a : lats) items += (long long)((a.p.nx + 59) / 60) * a.p.ny + 7;
     L.max_items = (int)std::min<long long>(items, INT32_MAX);
-    // Fused two-step tiles: strips of TW2 columns, at most one row per segment.
+    // Fused two-step tiles: strips of at least the narrowest width's output
+    // columns, at most one row per segment.
     long long items2 = 0;
-    for (const auto& a : lats) items2 += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * a.p.ny + 7;
+    for (const auto& a : lats) {
+        const int tw = lbk::fuse2_tw(a.p.storage, lbk::FUSE2_NW_MIN);
+        items2 += (long long)((a.p.nx + tw - 1) / tw) * a.p.ny + 7;
+    }
     L.max_items2 = (int)std::min<long long>(items2, INT32_MAX);
     L.off_tiles = L.off_res + align_up(sizeof(double) * (8 + 2 * n), ALIGN);
     L.off_tiles2 = L.off_tiles + align_up(sizeof(int32_t) * (size_t)L.max_items, ALIGN);
@@ -133,9 +139,14 @@ Layout plan(std::vector<Lat>& lats)
         // profile accumulator rows: one per 64 columns, or for the moment form
         // one per tile of the narrowest launch shape (60 collided columns)
         a.ngroups = is_mom(a.p.storage) ? (a.p.nx + 59) / 60 : (a.p.nx + 63) / 64;
-        // and, for FP32 populations, the fused two-step kernel's partials:
-        // two steps x strips of TW2 columns x four waves
-        a.ngroups2 = a.p.storage == LB_F32 ? 8 * ((a.p.nx + lbk::TW2 - 1) / lbk::TW2) : 0;
+        // and, for the storages with a fused two-step kernel, its partials:
+        // two steps x strips x waves per step, for the widest of its layouts
+        a.ngroups2 = 0;
+        if (fusion_storage(a.p.storage))
+            for (int nw = lbk::FUSE2_NW_MIN; nw <= lbk::FUSE2_NW_MAX; ++nw) {
+                const int tw = lbk::fuse2_tw(a.p.storage, nw);
+                a.ngroups2 = std::max(a.ngroups2, 2 * nw * ((a.p.nx + tw - 1) / tw));
+            }
         // Each state buffer also serves as staging for four FP64 arrays of
         // nx*ny values (initial fields, field reads): at least 32 bytes per
         // site, whatever the storage needs (6 FP32 moments need only 24).
@@ -231,6 +242,8 @@ struct lbb_handle {
     int fusion = 1;                  // time steps per step-kernel pass: 1, or 2 (k_step2)
     int ly2 = 0;                     // rows per fused tile as set (0: automatic)
     int ly2_eff = 0;                 // rows per fused tile in effect (the automatic choice resolved)
+    int fnw = 0;                     // waves per step of the fused kernel as set (0: automatic)
+    int fnw_eff = 2;                 // the same in effect
     int ntot2 = 0;
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // graph starting from buffer 0 / 1
     int watchdog = 0;
@@ -261,14 +274,15 @@ void drop_graphs(lbb_handle* h)
 }
 
 // Makespan, in ticks, of the fused tiles of height ly2 listed lattice by
-// lattice and scheduled greedily on ncu compute units.
-long long fused_makespan(const lbb_handle* h, int ly2, int ncu)
+// lattice and scheduled greedily on `slots` concurrent blocks.
+long long fused_makespan(const lbb_handle* h, int ly2, int slots)
 {
     std::priority_queue<long long, std::vector<long long>, std::greater<long long>> free_at;
-    for (int c = 0; c < ncu; ++c) free_at.push(0);
+    for (int c = 0; c < slots; ++c) free_at.push(0);
     long long end = 0;
+    const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
     for (const Lat& a : h->lats) {
-        const int strips = (a.p.nx + lbk::TW2 - 1) / lbk::TW2;
+        const int strips = (a.p.nx + tw - 1) / tw;
         const int lh = std::min(ly2, a.p.ny);
         for (int st = 0; st < strips; ++st)
             for (int y = 0; y < a.p.ny; y += lh) {
@@ -281,22 +295,31 @@ long long fused_makespan(const lbb_handle* h, int ly2, int ncu)
     return end;
 }
 
-// Automatic fused tile height: the candidate with the smallest makespan (ties:
-// the taller tiles, fewer of them).  Candidates: fixed heights and, for each
-// number of rounds r = 1..4, the smallest height whose tiles fit r rounds.
-int auto_ly2(const lbb_handle* h)
+int device_cus()
 {
-    int dev = 0, ncu = 256, maxny = 1;
+    int dev = 0, ncu = 256;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         ncu = prop.multiProcessorCount;
+    return ncu;
+}
+
+// Automatic fused tile height: the candidate with the smallest makespan (ties:
+// the taller tiles, fewer of them) on the blocks the device runs at once.
+// Candidates: fixed heights and, for each number of rounds r = 1..4, the
+// smallest height whose tiles fit r rounds.
+int auto_ly2(const lbb_handle* h)
+{
+    int maxny = 1;
+    const int ncu = device_cus() * std::max(1, lbk::step2_blocks_per_cu(h->storage, h->fnw_eff));
+    const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
     for (const Lat& a : h->lats) maxny = std::max(maxny, a.p.ny);
     std::vector<int> cand = {16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512};
     for (int r = 1; r <= 4; ++r) {
         for (int l2 = 16; l2 < maxny; ++l2) {
             long long it = 0;
             for (const Lat& a : h->lats)
-                it += (long long)((a.p.nx + lbk::TW2 - 1) / lbk::TW2) * ((a.p.ny + l2 - 1) / l2);
+                it += (long long)((a.p.nx + tw - 1) / tw) * ((a.p.ny + l2 - 1) / l2);
             if (it <= (long long)r * ncu) { cand.push_back(l2); break; }
         }
     }
@@ -307,6 +330,23 @@ int auto_ly2(const lbb_handle* h)
         if (c < 1 || c > maxny) continue;
         const long long t = fused_makespan(h, c, ncu);
         if (best_t < 0 || t < best_t || (t == best_t && c > best)) { best_t = t; best = c; }
+    }
+    return best;
+}
+
+// Automatic waves per step of the fused kernel: the most waves the device
+// keeps on one compute unit (blocks per CU x waves per block); ties go to the
+// wider tiles (less overlap).  Only blocks whose waves spread evenly over a
+// CU's four SIMDs (4 or 8 waves) are candidates: six-wave blocks leave two
+// SIMDs with one step's waves only and measured 20-35 % slower.  2 where no
+// fused kernel exists for the storage.
+int auto_fnw(const lbb_handle* h)
+{
+    int best = 2, best_w = -1;
+    if (!fusion_storage(h->storage)) return best;
+    for (int nw : {2, 4}) {
+        const int w = lbk::step2_blocks_per_cu(h->storage, nw) * 2 * nw;
+        if (w >= best_w) { best_w = w; best = nw; }
     }
     return best;
 }
@@ -337,19 +377,21 @@ lb_status decompose(lbb_handle* h)
     }
     if (item > h->lay.max_items) return fail(LB_EINVAL, "launch shape gives more work items than planned");
     h->ntot = item;
-    // Fused two-step tiles: TW2 columns x ly2 rows.  ly2 = 0 picks the height
+    // Fused two-step tiles: fuse2_tw columns x ly2 rows.  ly2 = 0 picks the height
     // whose tiles, handed to the compute units in table order (each takes the
     // next tile when it finishes one), finish first; a tile of h rows costs
     // h + 8 ticks (the overlap rows of the two steps), whatever its width.
+    h->fnw_eff = h->fnw > 0 ? h->fnw : auto_fnw(h);
     int ly2 = h->ly2;
     if (ly2 <= 0) ly2 = auto_ly2(h);
     h->ly2_eff = ly2;
+    const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
     int item2 = 0;
     h->tiles2.clear();
     for (size_t k = 0; k < h->lats.size(); ++k) {
         const Lat& a = h->lats[k];
         lbk::LatDesc& d = h->descs[k];
-        d.nstrip2 = (a.p.nx + lbk::TW2 - 1) / lbk::TW2;
+        d.nstrip2 = (a.p.nx + tw - 1) / tw;
         d.ly2 = std::min(ly2, a.p.ny);
         d.nseg2 = (a.p.ny + d.ly2 - 1) / d.ly2;
         d.nitems2 = d.nstrip2 * d.nseg2;
@@ -389,7 +431,7 @@ lb_status launch_one(lbb_handle* h, hipStream_t s, int src, int first = 0)
 // Steps t and t+1 in one launch: reads buffer src, writes buffer src ^ 1.
 lb_status launch_two(lbb_handle* h, hipStream_t s, int src)
 {
-    hipError_t e = lbk::launch_step2(h->storage, h->base, h->d_desc(), h->d_tiles2(), h->ntot2, src,
+    hipError_t e = lbk::launch_step2(h->storage, h->fnw_eff, h->base, h->d_desc(), h->d_tiles2(), h->ntot2, src,
                                      std::max(1, h->ntot2), s);
     if (e != hipSuccess) return fail(LB_EDEVICE, "fused step launch failed: %s", hipGetErrorString(e));
     return LB_OK;
@@ -768,24 +810,60 @@ lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
     return decompose(h);
 }
 
-// Two time steps per pass (k_step2): FP32 population storage.  ly2 = 0 picks
-// the tile height.
+// Whether the handle may run two steps per pass: FP32 or 16-bit population
+// storage (the 16-bit forms take their halo columns in aligned pairs: every
+// lattice needs an even nx).
+bool fusion_allowed(const lbb_handle* h)
+{
+    if (!fusion_storage(h->storage)) return false;
+    if (h->storage != LB_F32)
+        for (const Lat& a : h->lats)
+            if (a.p.nx % 2) return false;
+    return true;
+}
+
+// The fused kernel's LDS for nw waves per step, checked against the device.
+lb_status check_fused_lds(const lbb_handle* h, int nw)
+{
+    int dev = 0, lim = 65536;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t need = lbk::step2_lds_bytes(h->storage, nw);
+    if (need == 0 || need > (size_t)lim)
+        return fail(LB_EINVAL, "two steps per pass with %d lanes per step need %zu bytes of LDS per block, the device "
+                    "allows %d", 64 * nw, need, lim);
+    return LB_OK;
+}
+
+// Two time steps per pass (k_step2): FP32 or 16-bit population storage.
+// ly2 = 0 picks the tile height.
 lb_status set_fusion(lbb_handle* h, int k, int ly2)
 {
     if (k != 1 && k != 2) return fail(LB_EINVAL, "steps per pass must be 1 or 2");
     if (ly2 < 0) return fail(LB_EINVAL, "ly2 must be >= 0");
     if (k == 2) {
-        if (h->storage != LB_F32) return fail(LB_EINVAL, "two steps per pass need FP32 population storage");
-        int dev = 0, lim = 65536;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        const size_t need = lbk::step2_lds_bytes(h->storage);
-        if (need == 0 || need > (size_t)lim)
-            return fail(LB_EINVAL, "two steps per pass need %zu bytes of LDS per block, the device allows %d", need,
-                        lim);
+        if (!fusion_allowed(h))
+            return fail(LB_EINVAL, "two steps per pass need FP32 or 16-bit population storage (16-bit: even nx)");
+        const int nw = h->fnw > 0 ? h->fnw : auto_fnw(h);
+        lb_status st = check_fused_lds(h, nw);
+        if (st != LB_OK) return st;
     }
     h->fusion = k;
     h->ly2 = ly2;
+    return decompose(h);
+}
+
+// Lanes per step of the fused kernel's blocks: 128, 192 or 256 (0: automatic).
+lb_status set_fusion_tile(lbb_handle* h, int lanes)
+{
+    if (lanes != 0 && lanes != 128 && lanes != 192 && lanes != 256)
+        return fail(LB_EINVAL, "fused tile lanes must be 0, 128, 192 or 256 (got %d)", lanes);
+    const int nw = lanes / 64;
+    if (nw && fusion_storage(h->storage)) {
+        lb_status st = check_fused_lds(h, nw);
+        if (st != LB_OK) return st;
+    }
+    h->fnw = nw;
     return decompose(h);
 }
 
@@ -826,8 +904,6 @@ lb_status time_steps(lbb_handle* h, int32_t n, double* ms)
 
 using lbh::TuneEntry;
 
-// Whether the handle may run two steps per pass (set_fusion's storage condition).
-bool fusion_allowed(const lbb_handle* h) { return h->storage == LB_F32; }
 
 std::string arch_name()
 {
@@ -882,6 +958,10 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
             lb_status st = set_launch(h, kv.second.bx, kv.second.ly, kv.second.grid);
             if (st != LB_OK) return st;
             const bool fuse = kv.second.fusion == 2 && fusion_allowed(h);
+            if (fuse) {
+                st = set_fusion_tile(h, kv.second.fw);
+                if (st != LB_OK) return st;
+            }
             st = set_fusion(h, fuse ? 2 : 1, fuse ? kv.second.ly2 : 0);
             if (st != LB_OK) return st;
             if (best_out) *best_out = kv.second;
@@ -909,7 +989,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     const int cur = h->cur;
     const int64_t t = h->t, ns = h->nsamples;
     const int bx0 = h->bx, ly0 = h->ly, grid0 = h->grid, gs0 = h->graph_steps, wd0 = h->watchdog;
-    const int fu0 = h->fusion, ly20 = h->ly2;
+    const int fu0 = h->fusion, ly20 = h->ly2, fnw0 = h->fnw;
     h->graph_steps = 0;
     h->watchdog = 0;
     h->fusion = 1;          // the single-step kernel's shapes are what is tuned
@@ -945,18 +1025,29 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
         if (st != LB_OK) break;
     }
     // two steps per pass behind the best single-step shape (which any odd
-    // remaining step uses): the automatic tile height (about one tile per
-    // CU) and shorter tiles, which balance batches of uneven lattices
+    // remaining step uses): each block width the device grants, at the
+    // automatic tile height (the smallest makespan on the blocks resident at
+    // once) and shorter tiles, which balance batches of uneven lattices
     if (st == LB_OK && best.bx && fusion_allowed(h)) {
         st = set_launch(h, best.bx, best.ly, best.grid);
-        for (int ly2 : {0, 64, 128, 256}) {
+        for (int lanes : {128, 192, 256}) {
             if (st != LB_OK) break;
-            if (ly2 && ly2 >= maxny) continue;
-            st = set_fusion(h, 2, ly2);
-            if (st == LB_OK) st = steps_direct_warm(h, 2);
-            double ms = 0;
-            if (st == LB_OK) st = time_steps(h, steps + (steps & 1), &ms);
-            if (st == LB_OK && ms < best.ms) { best.fusion = 2; best.ly2 = ly2; best.ms = ms; }
+            if (lbk::step2_blocks_per_cu(h->storage, lanes / 64) < 1) continue;
+            st = set_fusion_tile(h, lanes);
+            for (int ly2 : {0, 64, 128, 256}) {
+                if (st != LB_OK) break;
+                if (ly2 && ly2 >= maxny) continue;
+                st = set_fusion(h, 2, ly2);
+                if (st == LB_OK) st = steps_direct_warm(h, 2);
+                double ms = 0;
+                if (st == LB_OK) st = time_steps(h, steps + (steps & 1), &ms);
+                if (st == LB_OK && ms < best.ms) {
+                    best.fusion = 2;
+                    best.ly2 = ly2;
+                    best.fw = lanes;
+                    best.ms = ms;
+                }
+            }
         }
         h->fusion = 1;
     }
@@ -975,6 +1066,7 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     h->graph_steps = gs0;
     h->fusion = fu0;
     h->ly2 = ly20;
+    h->fnw = fnw0;
     h->watchdog = wd0;
     if (st != LB_OK) {
         (void)set_launch(h, bx0, ly0, grid0);
@@ -982,6 +1074,10 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     }
     st = set_launch(h, best.bx, best.ly, best.grid);
     if (st != LB_OK) return st;
+    if (best.fusion == 2) {
+        st = set_fusion_tile(h, best.fw);
+        if (st != LB_OK) return st;
+    }
     st = set_fusion(h, best.fusion, best.ly2);
     if (st != LB_OK) return st;
     if (best_out) *best_out = best;
@@ -1144,6 +1240,18 @@ lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2)
 {
     CHECK_H(h);
     return set_fusion(&h->b, steps_per_pass, ly2);
+}
+
+lb_status lb_set_fusion_tile(lb_handle* h, int32_t lanes)
+{
+    CHECK_H(h);
+    return set_fusion_tile(&h->b, lanes);
+}
+
+lb_status lb_get_fusion_tile(lb_handle* h, int32_t* lanes, int32_t* columns)
+{
+    CHECK_H(h);
+    return lbb_get_fusion_tile(&h->b, lanes, columns);
 }
 
 lb_status lb_get_launch(lb_handle* h, int32_t* bx, int32_t* ly, int32_t* steps_per_pass, int32_t* ly2)
@@ -1310,6 +1418,20 @@ lb_status lbb_set_fusion(lbb_handle* h, int32_t steps_per_pass, int32_t ly2)
 {
     CHECK_H(h);
     return set_fusion(h, steps_per_pass, ly2);
+}
+
+lb_status lbb_set_fusion_tile(lbb_handle* h, int32_t lanes)
+{
+    CHECK_H(h);
+    return set_fusion_tile(h, lanes);
+}
+
+lb_status lbb_get_fusion_tile(lbb_handle* h, int32_t* lanes, int32_t* columns)
+{
+    CHECK_H(h);
+    if (lanes) *lanes = 64 * h->fnw_eff;
+    if (columns) *columns = lbk::fuse2_tw(h->storage, h->fnw_eff);
+    return LB_OK;
 }
 
 lb_status lbb_get_launch(lbb_handle* h, int32_t* bx, int32_t* ly, int32_t* grid, int32_t* steps_per_pass,

@@ -124,6 +124,8 @@ bool parse_line(const std::string& line, std::pair<std::string, TuneEntry>* out)
     if (fu < 0) return false;
     if (fu == 0) e.fusion = 1;
     if (get_int(body, "ly2", 0, 1 << 20, &e.ly2) < 0) return false;
+    if (get_int(body, "fw", 0, 256, &e.fw) < 0) return false;
+    if (e.fw != 0 && e.fw != 128 && e.fw != 192 && e.fw != 256) return false;
     if (get_double(body, "ms", &e.ms) < 0) return false;
     out->first = key;
     out->second = e;
@@ -167,8 +169,9 @@ std::string format_cache(const TuneCache& ents)
     for (size_t i = 0; i < ents.size(); ++i) {
         char buf[256];
         const TuneEntry& e = ents[i].second;
-        snprintf(buf, sizeof buf, "{\"bx\": %d, \"ly\": %d, \"grid\": %d, \"fusion\": %d, \"ly2\": %d, \"ms\": %.6f}%s\n",
-                 e.bx, e.ly, e.grid, e.fusion, e.ly2, e.ms, i + 1 < ents.size() ? "," : "");
+        snprintf(buf, sizeof buf,
+                 "{\"bx\": %d, \"ly\": %d, \"grid\": %d, \"fusion\": %d, \"ly2\": %d, \"fw\": %d, \"ms\": %.6f}%s\n",
+                 e.bx, e.ly, e.grid, e.fusion, e.ly2, e.fw, e.ms, i + 1 < ents.size() ? "," : "");
         s += "\"" + ents[i].first + "\": " + buf;
     }
     s += "}\n";

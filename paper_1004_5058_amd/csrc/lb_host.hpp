@@ -31,16 +31,18 @@ lb_status validate(const lb_params* p, int storage0, std::string* msg);
 struct TuneEntry {
     int bx = 0, ly = 0, grid = 0;
     int fusion = 1, ly2 = 0;   // time steps per pass and fused tile height (0: automatic)
+    int fw = 0;                // fused kernel's lanes per step: 128, 192, 256 (0: automatic)
     double ms = 0;
 };
 using TuneCache = std::vector<std::pair<std::string, TuneEntry>>;
 
 // Parses the cache text: one entry per line,
-//   "key": {"bx": 512, "ly": 128, "grid": 0, "fusion": 2, "ly2": 0, "ms": 0.35},
+//   "key": {"bx": 512, "ly": 128, "grid": 0, "fusion": 2, "ly2": 0, "fw": 128, "ms": 0.35},
 // Lines that are not of that form, keys with a quote or control character,
 // and entries whose numbers are missing, malformed or out of range (bx not in
-// {64, 128, 256, 512}, negative ly / grid / ly2, fusion not 1 or 2, ms not
-// finite) are skipped; an entry without "fusion" runs one step per pass.
+// {64, 128, 256, 512}, negative ly / grid / ly2, fusion not 1 or 2, fw not in
+// {0, 128, 192, 256}, ms not finite) are skipped; an entry without "fusion"
+// runs one step per pass, one without "fw" the automatic fused width.
 TuneCache parse_cache(const char* text, size_t len);
 // Reads and parses a cache file (missing or unreadable: empty).
 TuneCache read_cache(const char* path);

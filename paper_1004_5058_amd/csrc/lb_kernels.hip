@@ -684,49 +684,78 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
 
 // ------------------------------------------------------ two fused steps ---
 //
-// Steps t and t+1 in one pass over HBM.  A block of 512 threads owns a tile
-// of TW2 = 250 output columns x ly2 rows; thread j of each half of the block
-// holds column X - 3 + j (periodic).  Waves 0..3 run step t as k_step does
-// with x0 = X - 3 on rows y0-3 .. y1+2, but push the post-collision
-// populations into a four-row LDS ring instead of HBM.  Waves 4..7 run step
-// t+1 behind them: in the tick in which step t collides row a they pull row
-// a-3's populations from that ring (the shift in x of the layout becomes a
-// shift of the ring column) and stage its psi/rho, then collide row a-5;
-// they cover rows y0-2 .. y1+1 (staged) and y0 .. y1-1 (collided, columns
-// X .. X+249, stored to HBM).  Both halves meet at one LDS barrier per tick.  The step
-// t+1 pipeline runs, per row, exactly the operations of k_step on values
-// rounded to the storage format, so the pair of steps is bitwise that of two
-// k_step launches; each population crosses HBM once per two updates.
-template <class P>
-__global__ void __launch_bounds__(512)
+// Steps t and t+1 in one pass over HBM.  A block of 2 BW threads (BW = 64 NW
+// lanes per step) owns a tile of TW output columns x ly2 rows; thread j of
+// each half holds column X - XO + j (periodic), X the tile's first output
+// column.  Waves 0..NW-1 run step t as k_step does with x0 = X - XO on rows
+// y0-3 .. y1+2, but push the post-collision populations into an LDS ring
+// instead of HBM.  Waves NW..2NW-1 run step t+1 behind them: in the tick in
+// which step t collides row a they pull row a-3's populations from that ring
+// (the shift in x of the layout becomes a shift of the ring column) and stage
+// its psi/rho, then collide row a-5; they cover rows y0-2 .. y1+1 (staged)
+// and y0 .. y1-1 (collided, columns X .. X+TW-1, stored to HBM).  Both halves
+// meet at one LDS barrier per tick.  The step t+1 pipeline runs, per row,
+// exactly the operations of k_step on values rounded to the storage format,
+// so the pair of steps is bitwise that of two k_step launches; each
+// population crosses HBM once per two updates.
+//
+// Column offset XO: 4-byte storage 3 (TW = BW - 6).  2-byte storage 4
+// (TW = BW - 8): step t's tile then starts at an even column, so its halo
+// columns come in aligned column pairs, as in k_step (needs an even nx).
+//
+// The population ring is split by the y direction of the population, since
+// each class lives for a different number of ticks (rows r written at
+// tick w, read by step t+1 at tick r+3, before that tick's barrier):
+//   c_y = +1 (2, 5, 6): written at tick r-1 (row 0 at a bottom wall: tick 0), four rows;
+//   c_y =  0 (0, 1, 3): written at tick r, three rows;
+//   c_y = -1 (4, 7, 8): written at tick r+1, two rows; at a top wall the
+//     populations that return into row ny-1 are computed at tick ny-1 and
+//     held in registers until tick ny, when the slot's previous row is read.
+// Nine rows of six planes instead of four rows of eighteen; with the
+// five-row rho ring (the rho stencil is belt 1 only) three blocks of 128
+// FP32 lanes per step fit in a CU's 160 KiB of LDS.
+template <class P> struct Fuse2Geom {
+    static constexpr int XO = sizeof(typename P::S) == 2 ? 4 : 3;
+};
+constexpr int pr_class(int cy) { return cy > 0 ? 0 : (cy == 0 ? 1 : 2); }
+// index of direction i within its class: (2, 5, 6), (0, 1, 3), (4, 7, 8)
+constexpr int pr_k(int i) { return (i == 2 || i == 0 || i == 4) ? 0 : ((i == 5 || i == 1 || i == 7) ? 1 : 2); }
+
+template <class P, int NW>
+__global__ void __launch_bounds__(128 * NW)
 k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __restrict__ tiles, int ntot,
         int src)
 {
-    constexpr int BX = 256;
+    constexpr int BW = 64 * NW;
     using S = typename P::S;
     using C = typename P::C;
     using C2 = typename V2<C>::T;
-    // 4-byte storage only: the halo of step t is one dword per column and
-    // plane; the paired 2-byte window would start at the odd column X - 7
-    static_assert(sizeof(S) == 4, "two fused steps: 4-byte storage");
-    using HT = unsigned;
-    // psi and rho deviation rings of both steps, [step][slot][column index j + 2]
-    __shared__ C2 ringP[2][6][BX + 4];
-    __shared__ C2 ringR[2][6][BX + 4];
-    // step t+1's input: populations after streaming, logical row r in slot
-    // r & 3, plane q, index j + 1 (one spare entry each side for the values a
-    // wall returns to the neighbouring column)
-    __shared__ S pring[4][18][BX + 2];
-    __shared__ HT hst[4][18][4];
-    __shared__ C momx[2][BX];          // step t's wall momentum, handed to step t+1
+    static_assert(sizeof(S) <= 4, "two fused steps: 4- and 2-byte storage");
+    constexpr bool DMA16 = sizeof(S) == 2;
+    constexpr int XO = Fuse2Geom<P>::XO;
+    constexpr int TW = BW - 2 * XO;
+    using HT = std::conditional_t<DMA16, unsigned short, unsigned>;
+    // psi rings [step][slot][column index j + 2] (six rows), rho rings (five rows)
+    __shared__ C2 ringP[2][6][BW + 4];
+    __shared__ C2 ringR[2][5][BW + 4];
+    // step t+1's input, after streaming: class rows 0..3 (c_y = +1, slot r & 3),
+    // 4..6 (c_y = 0), 7..8 (c_y = -1, slot r & 1); six planes (species x the
+    // class's three directions); index j + 1, one spare entry each side for the
+    // values a wall returns to the neighbouring column
+    __shared__ S pring[9][6][BW + 2];
+    // direct-to-LDS halo columns of step t: HS rows (a multiple of the number
+    // of halo waves, so rows sharing a slot share a wave)
+    constexpr int HS = (NW == 3) ? 6 : 4;
+    __shared__ HT hst[HS][18][DMA16 ? 12 : 4];
+    __shared__ C momx[2][BW];          // step t's wall momentum, handed to step t+1
 
     const int tid = threadIdx.x;
-    const int role = __builtin_amdgcn_readfirstlane(tid >> 8);   // 0: step t, 1: step t+1
-    const int j = tid & (BX - 1);
-    const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) & 3), lane = tid & 63;
-    // step t's per-row halo work rotates over its four waves (rows r and r + 4
-    // share a slot of the halo ring and a wave)
-    auto halo_wave = [&](int r) { return r & 3; };
+    const int role = __builtin_amdgcn_readfirstlane(tid / BW);   // 0: step t, 1: step t+1
+    const int j = tid - role * BW;
+    const int wave = __builtin_amdgcn_readfirstlane(j >> 6), lane = tid & 63;
+    // step t's per-row halo work rotates over its waves
+    auto halo_wave = [&](int r) { return ((r % NW) + NW) % NW; };
+    auto hslot = [&](int r) { return ((r % HS) + HS) % HS; };
 
     for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
         const int L = tiles[w];
@@ -743,16 +772,16 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const int strip = lin % nstrip, seg = lin / nstrip;
         const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
         const long long plane = d.plane;
-        const int X = strip * TW2;
+        const int X = strip * TW;
         const int y0 = seg * d.ly2;
         const int y1 = min(y0 + d.ly2, ny);
         auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
-        const int x0 = X - 3;
+        const int x0 = X - XO;
         const unsigned xc = (unsigned)wrap(x0 + j);
         const unsigned xp = (xc + 1 == (unsigned)nx) ? 0u : xc + 1;
         const unsigned xm = (xc == 0) ? (unsigned)(nx - 1) : xc - 1;
         // the columns this tile stores and whose wall momentum it counts
-        const bool own = j >= 3 && j < 3 + TW2 && X + (j - 3) < nx;
+        const bool own = j >= XO && j < XO + TW && X + (j - XO) < nx;
 
         const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
         const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
@@ -776,16 +805,20 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const int es = (int)sizeof(S);
         const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
         const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
-        // step t's halo columns x0-2, x0-1, x0+BX, x0+BX+1 by direct-to-LDS
-        // loads, as in k_step
+        // step t's halo columns by direct-to-LDS loads, as in k_step.  4-byte
+        // storage, lanes 0..3: columns x0-2, x0-1, x0+BW, x0+BW+1 and their
+        // left and right neighbours; 2-byte storage, lanes 0..5: the column
+        // pairs starting at x0-4, x0-2, x0, x0+BW-2, x0+BW, x0+BW+2.
         unsigned vh = 0, vhl = 0, vhr = 0;
-        if (lane < 4) {
-            const int hc = (lane < 2) ? x0 - 2 + lane : x0 + BX + lane - 2;
+        if (lane < 6) {
+            const int hc = DMA16 ? ((lane < 3) ? x0 - 4 + 2 * lane : x0 + BW - 8 + 2 * lane)
+                                 : ((lane < 2) ? x0 - 2 + lane : x0 + BW + lane - 2);
             vh = (unsigned)wrap(hc) * es;
             vhl = (unsigned)wrap(hc - 1) * es;
             vhr = (unsigned)wrap(hc + 1) * es;
         }
-        const int ndma = 4;
+        const int ndma = DMA16 ? 6 : 4;
+        const int hb16 = (lane < 2) ? 2 + lane : 6 + lane;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
         // line profile: each wave adds the sum of u_x over its own columns of
@@ -793,6 +826,13 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         double* __restrict__ prof2 =
             d.off_prof >= 0 ? (double*)(base + d.off_prof) + (long long)d.ngroups * ny : nullptr;
         C mom_b = 0, mom_t = 0;
+        // populations returned into row ny - 1 at a top wall, held one tick,
+        // rounded to the storage format where they are computed (the
+        // conversion of the multiply-add's result then rounds as k_step's
+        // store of the same expression: for FP16 the compiler fuses the two
+        // into one multiply-add rounded once to FP16, which a later
+        // conversion of an FP32 value would not reproduce)
+        S held[2][3] = {{(S)0, (S)0, (S)0}, {(S)0, (S)0, (S)0}};
 
         using R = Row<P>;
         auto load = [&](R& fr, int r) {
@@ -808,40 +848,53 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         auto halo_fetch = [&](int r) {
             if (wave == halo_wave(r) && lane < ndma) {
                 const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+                const int hs = hslot(r);
 #pragma unroll
                 for (int q = 0; q < 18; ++q) {
                     const int cx = CX[q % 9];
-                    const unsigned vo = ro + (cx > 0 ? vhl : (cx < 0 ? vhr : vh));
+                    const unsigned vo = ro + ((!DMA16 && cx > 0) ? vhl : ((!DMA16 && cx < 0) ? vhr : vh));
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
+                        q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[hs][q][0], 4, vo,
                         __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
                 }
             }
         };
-        auto hval = [&](int r, int q) -> C { return (C)__builtin_bit_cast(float, hst[r & 3][q][lane]); };
+        auto hval = [&](int hs, int q) -> C {
+            if constexpr (DMA16) {
+                return (C)__builtin_bit_cast(S, hst[hs][q][hb16 - CX[q % 9]]);
+            } else {
+                return (C)__builtin_bit_cast(float, hst[hs][q][lane]);
+            }
+        };
         auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 8) % 6); };
+        auto slot5 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 10) % 5); };
+        // ring row of population class c (pr_class) for row r
+        auto prow = [&](int c, int r) {
+            return __builtin_amdgcn_readfirstlane(c == 0 ? (r & 3) : (c == 1 ? 4 + (r - y0 + 9) % 3 : 7 + (r & 1)));
+        };
 
         // Step t: stage row r (HBM populations in fr) into ring 0, plus the
         // four halo entries (lanes 0..3 of the row's halo wave).
         auto stage1 = [&](const R& fr, int r) {
-            const int slot = slot6(r);
+            const int sp = slot6(r), sr = slot5(r);
             C da, db;
             dens(fr, da, db);
-            ringP[0][slot][j + 2] = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
-            ringR[0][slot][j + 2] = C2{da, db};
+            ringP[0][sp][j + 2] = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
+            ringR[0][sr][j + 2] = C2{da, db};
             if (wave == halo_wave(r) && lane < 4) {
                 // the row's own loads have completed (da, db); its halo loads
                 // were issued before them, so their data is in LDS
                 asm volatile("" ::"v"(da), "v"(db) : "memory");
-                C ha = hval(r, 0), hb = hval(r, 9);
+                const int hs = hslot(r);
+                C ha = hval(hs, 0), hb = hval(hs, 9);
 #pragma unroll
                 for (int q = 1; q < 9; ++q) {
-                    ha += hval(r, q);
-                    hb += hval(r, 9 + q);
+                    ha += hval(hs, q);
+                    hb += hval(hs, 9 + q);
                 }
-                const int hidx = (lane < 2) ? lane : BX + lane;
-                ringP[0][slot][hidx] = C2{dpsi_of(ha, e0, inv_rho0), dpsi_of(hb, e1, inv_rho0)};
-                ringR[0][slot][hidx] = C2{ha, hb};
+                const int hidx = (lane < 2) ? lane : BW + lane;
+                ringP[0][sp][hidx] = C2{dpsi_of(ha, e0, inv_rho0), dpsi_of(hb, e1, inv_rho0)};
+                ringR[0][sr][hidx] = C2{ha, hb};
             }
         };
         // Step t+1: row r's populations from the LDS ring, pulled in x (column
@@ -849,44 +902,59 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         // even mirror: the bottom ones are written with their fluid rows 0 and
         // 1 (staged later), the top ones copy their staged fluid rows.
         auto stage2 = [&](R& fr, int r) {
-            const int slot = slot6(r);
+            const int sp = slot6(r), sr = slot5(r);
             if (walls && r >= ny) {
-                const int sm = slot6(2 * ny - 1 - r);
-                ringP[1][slot][j + 2] = ringP[1][sm][j + 2];
-                ringR[1][slot][j + 2] = ringR[1][sm][j + 2];
+                const int m = 2 * ny - 1 - r;
+                ringP[1][sp][j + 2] = ringP[1][slot6(m)][j + 2];
+                ringR[1][sr][j + 2] = ringR[1][slot5(m)][j + 2];
                 return;
             }
             if (walls && r < 0) return;
-            const int pr = r & 3;
+            int pr[3];
 #pragma unroll
-            for (int q = 0; q < 18; ++q) fr.v[q] = (C)pring[pr][q][j + 1 - CX[q % 9]];
+            for (int c = 0; c < 3; ++c) pr[c] = prow(c, r);
+#pragma unroll
+            for (int q = 0; q < 18; ++q) {
+                const int i = q % 9, s = q / 9;
+                const S v = pring[pr[pr_class(CY[i])]][3 * s + pr_k(i)][j + 1 - CX[i]];
+                if constexpr (DMA16) {
+                    if (q & 1) fr.v[q >> 1].y = v;
+                    else fr.v[q >> 1].x = v;
+                } else {
+                    fr.v[q] = (C)v;
+                }
+            }
             C da, db;
             dens(fr, da, db);
             const C2 pv = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
             const C2 rv = C2{da, db};
-            ringP[1][slot][j + 2] = pv;
-            ringR[1][slot][j + 2] = rv;
+            ringP[1][sp][j + 2] = pv;
+            ringR[1][sr][j + 2] = rv;
             if (walls && r <= 1 && -1 - r >= y0 - 2) {
-                const int sg = slot6(-1 - r);
-                ringP[1][sg][j + 2] = pv;
-                ringR[1][sg][j + 2] = rv;
+                ringP[1][slot6(-1 - r)][j + 2] = pv;
+                ringR[1][slot5(-1 - r)][j + 2] = rv;
             }
         };
 
         // Collide row y of step `k` (0: t, pushes into the LDS ring; 1: t+1,
         // stores to HBM).  The arithmetic is k_step's.
         auto collide = [&](const R& f, int y, int k) {
-            int sl[5];
+            int sl[5], sr[5];
             sl[0] = slot6(y - 2);
+            sr[0] = slot5(y - 2);
 #pragma unroll
-            for (int q = 1; q < 5; ++q) sl[q] = (sl[q - 1] == 5) ? 0 : sl[q - 1] + 1;
+            for (int q = 1; q < 5; ++q) {
+                sl[q] = (sl[q - 1] == 5) ? 0 : sl[q - 1] + 1;
+                sr[q] = (sr[q - 1] == 4) ? 0 : sr[q - 1] + 1;
+            }
             C ss[8];
-            stencil_sums<false, C>([&](int dy, int dx) { return ringP[k][sl[dy + 2]][j + 2 + dx]; },
-                            [&](int dy, int dx) { return ringR[k][sl[dy + 2]][j + 2 + dx]; }, ks0, ks1, kx1, kx2, ss);
+            stencil_sums<!std::is_same<S, float>::value, C>(
+                [&](int dy, int dx) { return ringP[k][sl[dy + 2]][j + 2 + dx]; },
+                [&](int dy, int dx) { return ringR[k][sr[dy + 2]][j + 2 + dx]; }, ks0, ks1, kx1, kx2, ss);
             const C sxA = ss[0], syA = ss[1], sxB = ss[2], syB = ss[3];
             const C cxA = ss[4], cyA = ss[5], cxB = ss[6], cyB = ss[7];
             const C2 p0 = ringP[k][sl[2]][j + 2];
-            const C2 r0c = ringR[k][sl[2]][j + 2];
+            const C2 r0c = ringR[k][sr[2]][j + 2];
             const C ra = rref0 + r0c.x, rb = rref1 + r0c.y;
             const C pa = pref0 + p0.x, pb = pref1 + p0.y;
             const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
@@ -897,12 +965,12 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                        + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
             const C inv_rho = rcp(ra + rb);
             const C ux = jx * inv_rho, uy = jy * inv_rho;
-            const int yw = (y < 0) ? y + ny : (y >= ny ? y - ny : y);   // periodic image of a step-t row
+            const int yw = ((y % ny) + ny) % ny;   // periodic image of a step-t row (any ny)
             const C gx = (body != nullptr) ? (C)body[yw] * inv_rho : (C)0;
             if (prof2 != nullptr && y >= y0 && y < y1) {
                 double su = own ? (double)ux : 0.0;
                 su = wave_sum(su);
-                if (lane == 0) prof2[((long long)(k * nstrip + strip) * 4 + wave) * ny + y] += su;
+                if (lane == 0) prof2[((long long)(k * nstrip + strip) * NW + wave) * ny + y] += su;
             }
             const bool bot = walls && (y == 0);
             const bool top = walls && (y == ny - 1);
@@ -910,6 +978,11 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
             const unsigned vrow_m = (unsigned)(ym * rbytes), vrow_0 = (unsigned)(y * rbytes),
                            vrow_p = (unsigned)(yp * rbytes);
+            int pr[3][3];   // ring rows of rows y-1, y, y+1 per class
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int dr = -1; dr <= 1; ++dr) pr[c][dr + 1] = prow(c, y + dr);
             auto relax_push = [&](int s, C rs, C drs, C Fx, C Fy) {
                 const C inv = rcp(rs);
                 const C vx = ux + tau * (Fx * inv + gx);
@@ -939,14 +1012,15 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                         const int cx = CX[i], cy = CY[i];
                         if (cy < 0 && bot) {
                             const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
-                            pring[y & 3][o + OPP[i]][j + 1 + cx] = (S)back;
+                            const int oi = OPP[i];
+                            pring[pr[pr_class(CY[oi])][1]][3 * s + pr_k(oi)][j + 1 + cx] = (S)back;
                             if (cx != 0 && count) mom_b += (C)cx * (fs[i] + back);
                         } else if (cy > 0 && top) {
                             const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
-                            pring[y & 3][o + OPP[i]][j + 1 + cx] = (S)back;
+                            held[s][pr_k(OPP[i])] = (S)back;   // written at tick ny
                             if (cx != 0 && count) mom_t += (C)cx * (fs[i] + back);
                         } else {
-                            pring[(y + cy) & 3][o + i][j + 1] = (S)fs[i];
+                            pring[pr[pr_class(cy)][cy + 1]][3 * s + pr_k(i)][j + 1] = (S)fs[i];
                         }
                     }
                     return;
@@ -983,6 +1057,19 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             relax_push(0, ra, r0c.x, FxA, FyA);
             relax_push(1, rb, r0c.y, FxB, FyB);
         };
+        // The populations a top wall returned into row ny - 1 (directions 4,
+        // 7, 8 at index j + c_ix of their source direction 2, 5, 6), written
+        // in the tick after that row's collision: row ny - 3, which shares
+        // their ring slot, has been read before this tick's barrier.
+        auto put_held = [&]() {
+            const int pr = prow(2, ny - 1);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                pring[pr][3 * s + pr_k(4)][j + 1] = held[s][pr_k(4)];
+                pring[pr][3 * s + pr_k(7)][j + 1 + CX[5]] = held[s][pr_k(7)];
+                pring[pr][3 * s + pr_k(8)][j + 1 + CX[6]] = held[s][pr_k(8)];
+            }
+        };
 
         // Step t collides rows A0 .. A1-1; tick a stages row a+2 and collides
         // row a of step t, and stages row a-3 and collides row a-5 of step
@@ -1009,6 +1096,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             load(F2, A0 + 2);
             stage1(F0, A0);
             stage1(F1, A0 + 1);
+            const bool top_here = walls && ny - 1 >= A0 && ny - 1 < A1;
             auto tick = [&](int a, const R& fc, const R& fs2, R& fl) {
                 if (a < A1) {
                     stage1(fs2, a + 2);
@@ -1019,6 +1107,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 }
                 lds_barrier();
                 if (a < A1 && (!walls || (a >= 0 && a < ny))) collide(fc, a, 0);
+                if (top_here && a == ny) put_held();
             };
             for (int a = A0; a <= T1; a += 4) {
                 tick(a, F0, F2, F3);
@@ -1918,17 +2007,73 @@ size_t step_lds_bytes(int storage, int bx, int ly)
     }
 }
 
-hipError_t launch_step2(int storage, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
-                        int grid, hipStream_t s)
+template <class P, int NW>
+static hipError_t step2_nw(char* base, const LatDesc* descs, const int* tiles, int ntot, int src, int grid,
+                           hipStream_t s)
 {
-    if (storage != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step2<StF32>), dim3(grid), dim3(512), 0, s, base, descs, tiles, ntot, src);
+    hipLaunchKernelGGL((k_step2<P, NW>), dim3(grid), dim3(128 * NW), 0, s, base, descs, tiles, ntot, src);
     return hipGetLastError();
 }
 
-size_t step2_lds_bytes(int storage)
+template <class P>
+static hipError_t step2_p(int nw, char* base, const LatDesc* descs, const int* tiles, int ntot, int src, int grid,
+                          hipStream_t s)
 {
-    return storage == 1 ? lds_of(k_step2<StF32>, 0) : 0;
+    switch (nw) {
+    case 2: return step2_nw<P, 2>(base, descs, tiles, ntot, src, grid, s);
+    case 3: return step2_nw<P, 3>(base, descs, tiles, ntot, src, grid, s);
+    case 4: return step2_nw<P, 4>(base, descs, tiles, ntot, src, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step2(int storage, int nw, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
+                        int grid, hipStream_t s)
+{
+    switch (storage) {
+    case 1: return step2_p<StF32>(nw, base, descs, tiles, ntot, src, grid, s);
+    case 2: return step2_p<StF16>(nw, base, descs, tiles, ntot, src, grid, s);
+    case 3: return step2_p<StBF16>(nw, base, descs, tiles, ntot, src, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class K>
+static int blocks_per_cu_of(K kernel, int threads)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kernel), threads, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+#define LBK_STEP2_CASES(F)                                                                          \
+    switch (storage * 10 + nw) {                                                                     \
+    case 12: return F((k_step2<StF32, 2>), 256);                                                     \
+    case 13: return F((k_step2<StF32, 3>), 384);                                                     \
+    case 14: return F((k_step2<StF32, 4>), 512);                                                     \
+    case 22: return F((k_step2<StF16, 2>), 256);                                                     \
+    case 23: return F((k_step2<StF16, 3>), 384);                                                     \
+    case 24: return F((k_step2<StF16, 4>), 512);                                                     \
+    case 32: return F((k_step2<StBF16, 2>), 256);                                                    \
+    case 33: return F((k_step2<StBF16, 3>), 384);                                                    \
+    case 34: return F((k_step2<StBF16, 4>), 512);                                                    \
+    default: return 0;                                                                               \
+    }
+
+size_t step2_lds_bytes(int storage, int nw)
+{
+#define LDS_F(K, T) lds_of(K, 0)
+    LBK_STEP2_CASES(LDS_F)
+#undef LDS_F
+}
+
+int step2_blocks_per_cu(int storage, int nw)
+{
+#define OCC_F(K, T) blocks_per_cu_of(K, T)
+    LBK_STEP2_CASES(OCC_F)
+#undef OCC_F
 }
 
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,

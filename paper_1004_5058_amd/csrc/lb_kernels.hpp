@@ -12,12 +12,19 @@ namespace lbk {
 // reads the local equilibria in place instead of pulling from neighbours).
 hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, const int* tiles, int ntot,
                        int src, int first, int grid, int ly, hipStream_t s);
-// Steps t and t+1 in one launch (k_step2, 512 threads, tiles of TW2 columns):
-// reads buffer src, writes buffer src ^ 1.  FP32 storage (code 1) only.
-constexpr int TW2 = 250;
-hipError_t launch_step2(int storage, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
+// Steps t and t+1 in one launch (k_step2): reads buffer src, writes buffer
+// src ^ 1.  FP32 and 16-bit storage (codes 1, 2, 3); nw = 2, 3 or 4 waves per
+// step, blocks of 128 nw threads, tiles of fuse2_tw(storage, nw) output
+// columns (the step t+1 columns of a 64 nw lane strip less the overlap).
+constexpr int fuse2_xo(int storage) { return (storage == 2 || storage == 3) ? 4 : 3; }
+constexpr int fuse2_tw(int storage, int nw) { return 64 * nw - 2 * fuse2_xo(storage); }
+constexpr int FUSE2_NW_MIN = 2, FUSE2_NW_MAX = 4;
+hipError_t launch_step2(int storage, int nw, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
                         int grid, hipStream_t s);
-size_t step2_lds_bytes(int storage);
+// LDS bytes of one fused block, and how many blocks the device keeps on one
+// compute unit (0: no such kernel).
+size_t step2_lds_bytes(int storage, int nw);
+int step2_blocks_per_cu(int storage, int nw);
 // Shared memory (bytes) one step block needs for tile width bx and ly rows;
 // 0 if the storage has no step kernel of that width.
 size_t step_lds_bytes(int storage, int bx, int ly);

@@ -74,6 +74,28 @@ def hb_fit(S, sigma, beta_grid=None, polish=True):
     return dict(sigma_y=sy, B=B, beta=beta, rss=rss)
 
 
+def hb_curve(rows):
+    """Herschel-Bulkley fits of one fixed-coupling flow curve (rows of
+    run_batched / run_plain): sigma against the nominal rate S = 2U/ny and
+    against the bulk rate S_bulk of the time-averaged profile (the paper's
+    measured dU/dy; points with S_bulk <= 0 are dropped), with the spread of
+    S_bulk / S and the largest relative difference of the two walls' stresses
+    (zero in a steady state)."""
+    S = np.array([r["S"] for r in rows], dtype=np.float64)
+    Sb = np.array([r["S_bulk"] for r in rows], dtype=np.float64)
+    sig = np.array([r["sigma"] for r in rows], dtype=np.float64)
+    steady = np.array([r["steady"] for r in rows], dtype=np.float64)
+    out = dict(points=int(S.size), nominal=hb_fit(S, sig))
+    ok = Sb > 0
+    out["bulk"] = hb_fit(Sb[ok], sig[ok]) if int(ok.sum()) >= 3 else None
+    out["bulk_points"] = int(ok.sum())
+    ratio = Sb / S
+    out["S_bulk_over_S"] = dict(median=float(np.median(ratio)), min=float(ratio.min()), max=float(ratio.max()))
+    out["wall_mismatch_max"] = float(steady.max())
+    out["wall_mismatch_median"] = float(np.median(steady))
+    return out
+
+
 def bulk_rate(profile):
     """Least-squares slope of U(y) over the central half of the channel."""
     ny = len(profile)

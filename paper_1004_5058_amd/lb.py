@@ -68,6 +68,10 @@ def load_library(path=LIB_PATH):
         "lb_step": [H, ctypes.c_int32],
         "lb_set_fusion": [H, ctypes.c_int32, ctypes.c_int32],
         "lbb_set_fusion": [H, ctypes.c_int32, ctypes.c_int32],
+        "lb_set_fusion_tile": [H, ctypes.c_int32],
+        "lbb_set_fusion_tile": [H, ctypes.c_int32],
+        "lb_get_fusion_tile": [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+        "lbb_get_fusion_tile": [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
         "lb_get_launch": [H] + [ctypes.POINTER(ctypes.c_int32)] * 4,
         "lbb_get_launch": [H] + [ctypes.POINTER(ctypes.c_int32)] * 5,
         "lb_fields": [H, _DP, _DP, _DP, _DP],
@@ -300,8 +304,19 @@ class Lattice:
         _check(_lib.lb_set_graph(self._h, int(steps_per_graph)))
 
     def set_fusion(self, steps_per_pass, ly2=0):
-        """1 or 2 time steps per pass of the step kernel (2: FP32 population storage)."""
+        """1 or 2 time steps per pass of the step kernel (2: FP32 or 16-bit
+        population storage; 16-bit needs an even nx)."""
         _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
+
+    def set_fusion_tile(self, lanes):
+        """Lanes per time step of the fused kernel's blocks: 128, 192, 256, or 0 (automatic)."""
+        _check(_lib.lb_set_fusion_tile(self._h, int(lanes)))
+
+    def fusion_tile(self):
+        """(lanes per step, stored columns per tile) of the fused kernel in effect."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lb_get_fusion_tile(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def launch(self):
         """The launch configuration in effect: dict(bx, ly, steps_per_pass, ly2),
@@ -311,8 +326,9 @@ class Lattice:
         return dict(zip(("bx", "ly", "steps_per_pass", "ly2"), (x.value for x in v)))
 
     def autotune(self, cache_path=None, steps=20):
-        """Pick the fastest launch shape, and for FP32 the steps per pass (state
-        preserved); returns (bx, ly, ms per step)."""
+        """Pick the fastest launch shape, and for FP32 and 16-bit storage the
+        steps per pass and fused block width (state preserved); returns
+        (bx, ly, ms per step)."""
         bx, ly, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         path = cache_path.encode() if cache_path else None
         _check(_lib.lb_autotune(self._h, path, int(steps), ctypes.byref(bx), ctypes.byref(ly), ctypes.byref(ms)))
@@ -429,8 +445,19 @@ class Batch:
         _check(_lib.lbb_set_graph(self._h, int(steps_per_graph)))
 
     def set_fusion(self, steps_per_pass, ly2=0):
-        """1 or 2 time steps per pass of the step kernel (2: FP32 population storage)."""
+        """1 or 2 time steps per pass of the step kernel (2: FP32 or 16-bit
+        population storage; 16-bit needs an even nx in every lattice)."""
         _check(_lib.lbb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
+
+    def set_fusion_tile(self, lanes):
+        """Lanes per time step of the fused kernel's blocks: 128, 192, 256, or 0 (automatic)."""
+        _check(_lib.lbb_set_fusion_tile(self._h, int(lanes)))
+
+    def fusion_tile(self):
+        """(lanes per step, stored columns per tile) of the fused kernel in effect."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lbb_get_fusion_tile(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def launch(self):
         """The launch configuration in effect: dict(bx, ly, grid, steps_per_pass,
@@ -445,7 +472,8 @@ class Batch:
         return ms.value
 
     def autotune(self, cache_path=None, steps=10):
-        """Pick the fastest launch shape and grid, and for FP32 the steps per pass
+        """Pick the fastest launch shape and grid, and for FP32 and 16-bit storage
+        the steps per pass and fused block width
         (state preserved); returns (bx, ly, grid, ms per step)."""
         bx, ly, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         path = cache_path.encode() if cache_path else None

@@ -338,6 +338,201 @@ def stress_controlled_points(cases, targets, method, lb_eval_many, S_lo, S_hi, s
     return solvers, rounds
 
 
+class RootSearch:
+    """Stress-controlled point with k lattice runs per round: the shear rate
+    in [S_lo, S_hi] at which a lattice's time-averaged wall stress equals
+    sigma_target to a relative tolerance tol, from lattice runs only (the
+    accepted point is the lattice run closest to the target among those
+    within tolerance).
+
+    Works in x = log S and t = asinh(sigma / SIGMA_UNIT).  The bracket
+    [lo, hi] holds the target's crossing: after each round it is narrowed to
+    the first pair of neighbouring results (lattice runs inside it, sorted in
+    x, with the bracket ends) that straddle the target.  placement:
+      "ksect"  k rates dividing the bracket into k + 1 equal parts (k = 1:
+               bisection);
+      "model"  k rates centred on a model's root, spread by h: at first the
+               root of model(x) = target with h = h0; after lattice results,
+               the root of the model shifted onto the nearest result
+               (model(x) + t_lattice - model(x_lattice)) with h halved each
+               round and never wider than the bracket allows.  model(x array)
+               -> t array is the network's curve at the case's couplings.
+    A bracket narrower than min_width with no accepted run means the flow
+    curve jumps across the target there: the search stops (jump = True)."""
+
+    def __init__(self, sigma_target, S_lo, S_hi, k=4, placement="ksect", model=None, h0=0.1, tol=0.01,
+                 min_width=1e-3, max_rounds=12):
+        self.target = float(sigma_target)
+        self.tt = float(to_target(sigma_target))
+        self.lo, self.hi = float(np.log(S_lo)), float(np.log(S_hi))
+        self.k = int(k)
+        self.placement = placement
+        if placement == "model" and model is None:
+            raise ValueError("model placement needs the network's curve")
+        self.model = model
+        self.h = float(h0)
+        self.tol = tol
+        self.min_width = min_width
+        self.max_rounds = max_rounds
+        self.rounds = 0
+        self.runs = 0
+        self.points = []            # (x, t, sigma) of every lattice run
+        self.result = None          # (S, sigma) once accepted
+        self.jump = False
+        self._pending = None
+
+    def done(self):
+        return self.result is not None or self.jump or self.rounds >= self.max_rounds
+
+    def _model_root(self, c=0.0):
+        """Root of model(x) + c = target inside the bracket (grid, linear
+        interpolation), the crossing nearest the bracket's centre; None if none."""
+        g = np.linspace(self.lo, self.hi, 257)
+        r = np.asarray(self.model(g), dtype=np.float64) + c - self.tt
+        cross = np.nonzero(np.signbit(r[:-1]) != np.signbit(r[1:]))[0]
+        if cross.size == 0:
+            return None
+        mid = 0.5 * (self.lo + self.hi)
+        q = cross[np.argmin(np.abs(g[cross] - mid))]
+        return float(g[q] - r[q] * (g[q + 1] - g[q]) / (r[q + 1] - r[q]))
+
+    def propose(self):
+        """The k rates of this round, or None when done."""
+        if self.done():
+            return None
+        w = self.hi - self.lo
+        if self.placement == "ksect":
+            xs = [self.lo + w * (i + 1) / (self.k + 1) for i in range(self.k)]
+        else:
+            if self.points:
+                # shift the model onto the lattice result nearest the bracket's centre
+                mid = 0.5 * (self.lo + self.hi)
+                xn, tn, _ = min(self.points, key=lambda p: abs(p[0] - mid))
+                c = tn - float(self.model(np.array([xn]))[0])
+                centre = self._model_root(c)
+            else:
+                centre = self._model_root()
+            if centre is None:
+                centre = 0.5 * (self.lo + self.hi)
+            h = min(self.h, w / (self.k + 1))
+            xs = [centre + h * (i - 0.5 * (self.k - 1)) for i in range(self.k)]
+            # inside the bracket: shift the pattern, else spread it over the bracket
+            if xs[0] <= self.lo or xs[-1] >= self.hi:
+                shift = max(self.lo + 0.5 * h - xs[0], min(0.0, self.hi - 0.5 * h - xs[-1]))
+                xs = [x + shift for x in xs]
+                if xs[0] <= self.lo or xs[-1] >= self.hi:
+                    xs = [self.lo + w * (i + 1) / (self.k + 1) for i in range(self.k)]
+            self.h *= 0.5
+        self._pending = xs
+        return [float(np.exp(x)) for x in xs]
+
+    def update(self, sigmas):
+        xs = self._pending
+        self._pending = None
+        self.rounds += 1
+        self.runs += len(sigmas)
+        ok = []
+        for x, s in zip(xs, sigmas):
+            self.points.append((x, float(to_target(s)), float(s)))
+            if abs(s - self.target) <= self.tol * abs(self.target):
+                ok.append((abs(s - self.target), x, float(s)))
+        if ok:
+            _, x, s = min(ok)
+            self.result = (float(np.exp(x)), s)
+            return
+        # narrow the bracket to the first straddling neighbours
+        inside = sorted((x, t) for x, t, _ in self.points if self.lo < x < self.hi)
+        seq = [(self.lo, -np.inf)] + inside + [(self.hi, np.inf)]
+        for (xa, ta), (xb, tb) in zip(seq[:-1], seq[1:]):
+            if ta < self.tt <= tb:
+                self.lo, self.hi = xa, xb
+                break
+        if self.hi - self.lo < self.min_width:
+            self.jump = True
+
+
+def search_batched(searches, lb_eval_many):
+    """Advance searches in lockstep rounds: each round gathers every open
+    search's k rates and runs them as one lattice batch.  lb_eval_many(list of
+    (search index, S)) -> list of sigma.  Returns the number of rounds."""
+    rounds = 0
+    while True:
+        todo = []
+        for k, s in enumerate(searches):
+            p = s.propose()
+            if p is not None:
+                todo.append((k, p))
+        if not todo:
+            return rounds
+        flat = [(k, S) for k, p in todo for S in p]
+        sig = lb_eval_many(flat)
+        o = 0
+        for k, p in todo:
+            searches[k].update(sig[o:o + len(p)])
+            o += len(p)
+        rounds += 1
+
+
+def rows_of(searches, cases):
+    """Training rows (couplings, S, sigma) of every lattice run of searches."""
+    rows = []
+    for s, (g1, g2, _) in zip(searches, cases):
+        rows += [dict(g_aa1=g1, g_aa2=g2, S=float(np.exp(x)), sigma=sig) for x, _, sig in s.points]
+    return rows
+
+
+def stream_points(cases_a, targets_a, cases_b, targets_b, lattice, S_lo, S_hi, k=4, use_network=False,
+                  surr=None, iters=4000, lr=3e-3, h0=0.1, log=None):
+    """Stress-controlled points for a stream of two batches of cases, batched:
+    batch A by k-section; batch B by k-section, or, with use_network, by
+    network placement, the network (surr, a FlowSurrogate) trained by the HIP
+    kernels on every lattice run of batch A (the runs the stream has made
+    anyway; no separate training ensemble).  lattice(list of (g1, g2, S)) ->
+    list of sigma.  Returns a report with wall times (training included),
+    lattice runs, rounds and accepted points per batch."""
+    import time as _t
+
+    def run(cases, targets, placement, model_of=None):
+        t0 = _t.perf_counter()
+        ss = []
+        for (g1, g2, _), t in zip(cases, targets):
+            ss.append(RootSearch(t, S_lo, S_hi, k=k, placement=placement,
+                                 model=model_of(g1, g2) if model_of else None, h0=h0))
+        rounds = search_batched(ss, lambda todo: lattice([(cases[j][0], cases[j][1], S) for j, S in todo]))
+        return ss, rounds, _t.perf_counter() - t0
+
+    out = {}
+    sa, ra, wa = run(cases_a, targets_a, "ksect")
+    out["A"] = _summary(sa, ra, wa)
+    t_train = 0.0
+    if use_network:
+        t0 = _t.perf_counter()
+        rows = rows_of(sa, cases_a)
+        surr.fit(rows, iters=iters, lr=lr)
+        t_train = _t.perf_counter() - t0
+        out["train"] = dict(rows=len(rows), wall_s=round(t_train, 3))
+        sb, rb, wb = run(cases_b, targets_b, "model", model_of=surr.curve)
+    else:
+        sb, rb, wb = run(cases_b, targets_b, "ksect")
+    out["B"] = _summary(sb, rb, wb)
+    acc = out["A"]["accepted"] + out["B"]["accepted"]
+    wall = wa + t_train + wb
+    out.update(accepted=acc, lattice_runs=out["A"]["lattice_runs"] + out["B"]["lattice_runs"],
+               wall_s=round(wall, 3), points_per_hour=round(acc * 3600.0 / wall, 1))
+    for s, t in zip(sa + sb, list(targets_a) + list(targets_b)):
+        if s.result is not None:
+            assert abs(s.result[1] - t) <= s.tol * abs(t)
+    if log:
+        log(out)
+    return out, sa, sb
+
+
+def _summary(ss, rounds, wall):
+    return dict(cases=len(ss), accepted=sum(s.result is not None for s in ss), jumps=sum(s.jump for s in ss),
+                lattice_runs=sum(s.runs for s in ss), rounds=rounds, wall_s=round(wall, 3),
+                status="".join("a" if s.result is not None else ("j" if s.jump else "c") for s in ss))
+
+
 # The stress-controlled setting the surrogate is trained and judged in: 256 x 128
 # Couette lattices, 20000 steps, common seeded start, couplings straddling the
 # edge of the emulsion region, wall speeds 6e-3 .. 6e-2.

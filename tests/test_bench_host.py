@@ -23,24 +23,36 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    entry = {"bytes_per_step": 123, "kernel_hash": bench.kernel_source_hash()}
-    (prof / "traffic.json").write_text(json.dumps({"w/f32": entry, "w/f16dev": dict(entry, kernel_hash="0" * 16)}))
+    entry = {"bytes_per_launch": 123, "kernel_hash": bench.kernel_source_hash()}
+    (prof / "traffic.json").write_text(json.dumps({"w/f32x2": entry, "w/f16x2": dict(entry, kernel_hash="0" * 16)}))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # the hash is of the real sources; only the summary's location moves
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: entry["kernel_hash"])
-    assert bench.measured_traffic("w", "f32") == 123
-    assert bench.measured_traffic("w", "f16dev") is None       # taken on another kernel source
-    assert bench.measured_traffic("w", "bf16dev") is None      # never measured
+    assert bench.measured_traffic("w", "f32x2") == 123
+    assert bench.measured_traffic("w", "f16x2") is None       # taken on another kernel source
+    assert bench.measured_traffic("w", "bf16x2") is None      # never measured
 
 
 def test_committed_counters_match_the_committed_kernels():
     """profiles/traffic.json is regenerated whenever the step kernel changes."""
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    assert d["couette_emulsion_4096x4096/f32"]["kernel_hash"] == bench.kernel_source_hash()
-    assert bench.measured_traffic("couette_emulsion_4096x4096", "f32") > 0
+    assert d["couette_emulsion_4096x4096/f32x2"]["kernel_hash"] == bench.kernel_source_hash()
+    assert bench.measured_traffic("couette_emulsion_4096x4096", "f32x2") > 0
 
 
-@pytest.mark.parametrize("storage,b", [("f32", 144), ("f16dev", 72), ("bf16dev", 72), ("mom32", 48), ("f64", 288)])
-def test_algorithmic_bytes_per_update(storage, b):
-    assert bench.BYTES_PER_LUP[storage] == b
+@pytest.mark.parametrize("variant,b,floor", [("f32x2", 144, 72), ("f32", 144, 144), ("f16x2", 72, 36),
+                                             ("bf16x2", 72, 36), ("f16dev", 72, 72), ("bf16dev", 72, 72),
+                                             ("mom32", 48, 48)])
+def test_bytes_per_update(variant, b, floor):
+    """Per-update bytes of one step per pass in the variant's storage (18 loads
+    + 18 stores, the moment form 6 + 6), and the bytes an update must move in
+    the variant as run (half with two steps per pass)."""
+    v = bench.VARIANTS[variant]
+    assert v["bytes_per_lup"] == b and v["floor_per_lup"] == floor
+    assert v["floor_per_lup"] * v["per_pass"] == v["bytes_per_lup"]
 
+
+def test_unknown_variant_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--variants", "f32x3"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "unknown variant" in r.stderr

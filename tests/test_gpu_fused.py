@@ -1,10 +1,12 @@
-"""Two time steps per pass (lb_set_fusion, FP32 storage): the fused kernel
-keeps step t's populations in on-chip memory and runs step t+1 behind it.  It
-performs the operations of two single steps on the same values (the library is
-built with multiply-add contraction inside expressions only), so populations,
-wall stresses and step counts must equal the single-step path bit for bit, with
-walls or periodic y, body force, any tile height, odd step counts (the last
-step runs alone) and graphs of either parity."""
+"""Two time steps per pass (lb_set_fusion; FP32, FP16- and BF16-deviation
+storage): the fused kernel keeps step t's populations in on-chip memory and
+runs step t+1 behind it.  It performs the operations of two single steps on the
+same values (the library is built with multiply-add contraction inside
+expressions only; the ring holds them rounded to the storage format, as HBM
+would), so populations, wall stresses and step counts must equal the
+single-step path bit for bit, with walls or periodic y, body force, any tile
+height and block width (128, 192, 256 lanes per step), odd step counts (the
+last step runs alone) and graphs of either parity."""
 import numpy as np
 import pytest
 
@@ -19,7 +21,7 @@ def _gpu():
     need_gpu()
 
 
-def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsion"):
+def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsion", lanes=0):
     u = 0.02 if walls else 0.0
     ra, rb = (inputs.emulsion(nx, ny, seed=seed) if init == "emulsion" else inputs.noise(nx, ny, seed))
     ux, uy = inputs.couette(nx, ny, u, -u) if walls else (None, None)
@@ -29,38 +31,62 @@ def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsio
         lat = gpu_lattice(nx, ny, ra, rb, ux, uy, walls=walls, u_top=u, u_bot=-u, storage=storage, **kw)
         lat.set_graph(graph)
         if fused:
+            lat.set_fusion_tile(lanes)
             lat.set_fusion(2, ly2)
+            if lanes:
+                assert lat.fusion_tile() == (lanes, lanes - (6 if storage == "f32" else 8))
         lat.step(steps)
         out.append((lat.populations(), lat.stress(), lat.time()))
         lat.close()
     return out
 
 
-@pytest.mark.parametrize("storage", ["f32"])
+@pytest.mark.parametrize("lanes", [128, 192, 256])
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
 @pytest.mark.parametrize("nx,ny,walls,body,ly2", [(600, 300, True, False, 0), (500, 120, False, True, 7),
                                                    (252, 31, True, True, 1), (8, 6, True, False, 64),
-                                                   (1000, 40, False, False, 0), (6, 2, False, False, 0)])
-def test_fused_bitwise_equals_single_steps(storage, nx, ny, walls, body, ly2):
-    (p1, s1, t1), (p2, s2, t2) = _pair(nx, ny, storage, walls, body, 30, ly2, 32)
+                                                   (1000, 40, False, False, 0), (6, 2, False, False, 0),
+                                                   (122, 3, True, False, 2), (244, 17, True, True, 0),
+                                                   (10, 2, False, True, 0)])
+def test_fused_bitwise_equals_single_steps(storage, nx, ny, walls, body, ly2, lanes):
+    (p1, s1, t1), (p2, s2, t2) = _pair(nx, ny, storage, walls, body, 30, ly2, 32, lanes=lanes)
     assert t1 == t2 == 30
     np.testing.assert_array_equal(p2, p1)
     assert s2 == s1
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
 @pytest.mark.parametrize("steps,graph", [(31, 0), (31, 6), (40, 6), (37, 32)])
-def test_fused_odd_steps_and_graph_parity(steps, graph):
+def test_fused_odd_steps_and_graph_parity(steps, graph, storage):
     """Odd step counts end with one single step; graphs of 6 steps hold three
     fused pairs (an odd number of buffer swaps per replay)."""
-    (p1, s1, t1), (p2, s2, t2) = _pair(333, 97, "f32", True, True, steps, 0, graph)
+    nx = 333 if storage == "f32" else 334
+    (p1, s1, t1), (p2, s2, t2) = _pair(nx, 97, storage, True, True, steps, 0, graph)
     assert t1 == t2 == steps
     np.testing.assert_array_equal(p2, p1)
     assert s2 == s1
 
 
-def test_fused_odd_width_fp32():
-    (p1, s1, _), (p2, s2, _) = _pair(257, 64, "f32", True, False, 20, 16, 32)
+@pytest.mark.parametrize("lanes", [128, 192, 256])
+def test_fused_odd_width_fp32(lanes):
+    (p1, s1, _), (p2, s2, _) = _pair(257, 64, "f32", True, False, 20, 16, 32, lanes=lanes)
     np.testing.assert_array_equal(p2, p1)
     assert s2 == s1
+
+
+@pytest.mark.parametrize("storage,tol", [("f16dev", 6e-5), ("bf16dev", 5e-4)])
+def test_fused_16bit_matches_oracle(storage, tol):
+    """16-bit deviation storage two steps per pass against the FP64 oracle,
+    100 steps (the tolerances of the single-step 16-bit parity tests)."""
+    nx, ny, u, steps = 300, 128, 0.01, 100
+    ra, rb = inputs.noise(nx, ny, 0)
+    p = oracle_params(nx, ny, True, u, -u)
+    g, _, _ = oracle_run(p, ra, rb, None, None, steps)
+    lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage)
+    lat.set_fusion(2)
+    lat.step(steps)
+    e = compare_fields(lat, p, g, tol)
+    print(f"\nfused {storage} {nx}x{ny}, {steps} steps: {e}")
 
 
 def test_fused_matches_oracle():
@@ -105,10 +131,13 @@ def test_fused_batch_equals_single_steps():
 def test_fused_refused_where_not_built():
     from paper_1004_5058_amd import lb
     ra, rb = inputs.noise(64, 16, 1)
-    for storage, kw in (("f64", {}), ("mom32", {}), ("f16dev", {}), ("bf16dev", {})):
-        lat = gpu_lattice(64, 16, ra, rb, storage=storage, **kw)
+    ra3, rb3 = inputs.noise(63, 16, 1)
+    for storage, (a, b) in (("f64", (ra, rb)), ("mom32", (ra, rb)), ("f16dev", (ra3, rb3)), ("bf16dev", (ra3, rb3))):
+        lat = gpu_lattice(b.shape[1], 16, a, b, storage=storage)
         with pytest.raises(lb.LBError, match="two steps per pass"):
             lat.set_fusion(2)
+        with pytest.raises(lb.LBError, match="lanes"):
+            lat.set_fusion_tile(64)
         lat.step(2)           # still steps, one step per pass
         lat.close()
 

@@ -93,19 +93,25 @@ def test_fp64_asymmetric_couplings_tau():
 
 
 def test_fp32_emulsion_parity():
-    """50/50 emulsion start (rho 1.0 / 0.1) with the linear Couette start, 50 steps."""
-    nx, ny, u = 128, 96, 0.05
+    """50/50 emulsion start (rho 1.0 / 0.1) with the linear Couette start, 100
+    steps: fields within 1e-6 (FP32 storage) and 1e-12 (FP64) of the oracle.
+    The time-averaged wall stress is a small difference of momentum fluxes
+    (here ~1e-3 of the diagonal populations that make it), so one rounding of
+    those populations (6e-8 relative) reaches it amplified about a
+    hundredfold: 1e-5 (FP32) and 1e-11 (FP64)."""
+    nx, ny, u, steps = 128, 96, 0.05, 100
     ra, rb = inputs.emulsion(nx, ny, seed=1)
     ux, uy = inputs.couette(nx, ny, u, -u)
     p = oracle_params(nx, ny, True, u, -u)
-    g, sb, st = oracle_run(p, ra, rb, ux, uy, 50)
-    for storage, tol in (("f64", 1e-12), ("f32", 1e-5)):
+    g, sb, st = oracle_run(p, ra, rb, ux, uy, steps)
+    for storage, tol, stol in (("f64", 1e-12, 1e-11), ("f32", 1e-6, 1e-5)):
         lat = gpu_lattice(nx, ny, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=storage)
-        lat.step(50)
+        lat.step(steps)
         e = compare_fields(lat, p, g, tol)
         gb, gt, _ = lat.stress()
-        assert abs(gb - sb) / abs(sb) < 10 * tol and abs(gt - st) / abs(st) < 10 * tol
-        print(storage, e)
+        es = max(abs(gb - sb) / abs(sb), abs(gt - st) / abs(st))
+        print(storage, e, f"stress {es:.2e}")
+        assert es < stol
 
 
 @pytest.mark.parametrize("bx,ly", [(64, 1), (64, 7), (128, 64), (256, 3), (256, 1000), (128, 2)])

@@ -107,3 +107,95 @@ def test_jump_across_target_stops():
         assert s.result is None and s.jump
         halvings = int(np.ceil(np.log2(np.log(S_HI / S_LO) / 1e-3)))
         assert s.runs <= (halvings + 2 if method == "bisect" else 3 * halvings)
+
+
+# ------------------------------------------------ k lattice runs per round ---
+
+from paper_1004_5058_amd.surrogate import RootSearch, search_batched, stream_points  # noqa: E402
+
+
+def _search(searches, curve):
+    calls = []
+
+    def many(todo):
+        calls.append(len(todo))
+        return [curve(S) for _, S in todo]
+    return search_batched(searches, many), calls
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8])
+def test_ksection_accepts_within_tolerance_in_the_rounds_its_bracket_implies(k):
+    """k-section shrinks the bracket (k + 1)-fold per round: on a continuous
+    curve the accepted run is within tolerance and the round count is at most
+    what the bracket reduction to the tolerance's width in log S implies."""
+    targets = hb(np.array([1.3e-4, 2.7e-4, 6.1e-4, 9.5e-4]))
+    ss = [RootSearch(t, S_LO, S_HI, k=k) for t in targets]
+    rounds, calls = _search(ss, hb)
+    for s, t in zip(ss, targets):
+        assert s.result is not None and abs(s.result[1] - t) <= 0.01 * t and s.result[1] == hb(s.result[0])
+        assert s.runs == k * s.rounds
+    # dt/dx >= 0.3 here, so any run within 0.01 / 0.3 in x of the root is accepted
+    need = int(np.ceil(np.log(np.log(S_HI / S_LO) / (2 * 0.01 / 0.3)) / np.log(k + 1))) + 1
+    assert rounds <= need
+    assert sum(calls) == sum(s.runs for s in ss)
+
+
+def test_model_placement_exact_model_accepts_in_one_round():
+    t = hb(3.3e-4)
+    s = RootSearch(t, S_LO, S_HI, k=4, placement="model", model=lambda x: to_target(hb(np.exp(x))), h0=0.05)
+    _search([s], hb)
+    assert s.rounds == 1 and s.result is not None
+
+
+def test_model_placement_with_a_level_error():
+    """A model with the right shape and a 20 % level error: the first round
+    (around its wrong root) gives the offset, the shifted model's root is then
+    the true root: two rounds at most."""
+    targets = hb(np.array([1.7e-4, 4.4e-4, 8.0e-4]))
+    ss = [RootSearch(t, S_LO, S_HI, k=4, placement="model", model=lambda x: to_target(1.2 * hb(np.exp(x))),
+                     h0=0.05) for t in targets]
+    _search(ss, hb)
+    for s, t in zip(ss, targets):
+        assert s.result is not None and s.rounds <= 2 and abs(s.result[1] - t) <= 0.01 * t
+
+
+def test_jump_across_the_target_stops_the_search():
+    """A curve that jumps over the target: no run can be within 1 %; the
+    bracket closes on the jump and the search reports it."""
+    def jumpy(S):
+        S = np.asarray(S)
+        return np.where(S < 4e-4, hb(S), 1.5 * hb(S))
+    t = 1.2 * hb(4e-4)
+    for placement, model in (("ksect", None), ("model", lambda x: to_target(hb(np.exp(x))))):
+        s = RootSearch(t, S_LO, S_HI, k=4, placement=placement, model=model)
+        _search([s], jumpy)
+        assert s.result is None and s.jump and s.rounds < s.max_rounds
+        assert abs(np.exp(s.lo) - 4e-4) / 4e-4 < 2e-3
+
+
+def test_stream_trains_on_its_own_runs_and_counts_everything():
+    """stream_points: batch A by k-section, the network fitted on exactly A's
+    lattice runs, batch B placed by it; every lattice call is counted and the
+    wall time includes the training."""
+    cases_a = [(-9.1, 8.0, 0.0)] * 3
+    cases_b = [(-9.1, 8.0, 0.0)] * 2
+    ta = list(hb(np.array([1.5e-4, 3.0e-4, 7.0e-4])))
+    tb = list(hb(np.array([2.2e-4, 5.5e-4])))
+    seen = []
+
+    def lattice(pts):
+        seen.extend(pts)
+        return [float(hb(S)) for _, _, S in pts]
+
+    class Fake:
+        def fit(self, rows, iters, lr):
+            self.rows = rows
+            return 0.0, 0.0
+
+        def curve(self, g1, g2):
+            return lambda x: to_target(1.05 * hb(np.exp(np.asarray(x))))
+    surr = Fake()
+    out, sa, sb = stream_points(cases_a, ta, cases_b, tb, lattice, S_LO, S_HI, k=4, use_network=True, surr=surr)
+    assert len(surr.rows) == sum(s.runs for s in sa) == out["A"]["lattice_runs"]
+    assert out["lattice_runs"] == len(seen) and out["accepted"] == 5
+    assert out["B"]["rounds"] <= 2 and out["train"]["rows"] == len(surr.rows)
