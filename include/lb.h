@@ -261,6 +261,17 @@ lb_status lbb_init(const lb_params* params, int32_t n, void* dev_state, size_t b
 lb_status lbb_step(lbb_handle* h, int32_t nsteps);
 /* Per-lattice time-averaged wall stresses (arrays of n) and sample count. */
 lb_status lbb_stress(lbb_handle* h, double* sig_bot, double* sig_top, int64_t* nsamples);
+/* lbb_stress for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results, bitwise, with the per-lattice reduction staged in a device array
+ * the library holds (16 bytes per lattice, 64 KiB on each GPU it runs on, until
+ * the process ends) instead of the caller's state, and no host or device
+ * allocation by the library.  Batches of at most 4096 lattices (LB_EINVAL
+ * beyond).  sig_bot / sig_top: host arrays of n doubles (either may be NULL).
+ * The handle's device must be current.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other threads or processes' streams)
+ * race.  Synchronises the handle's stream. */
+lb_status lbb_stress_noalloc(lbb_handle* h, double* sig_bot, double* sig_top, int64_t* nsamples);
 lb_status lbb_stress_reset(lbb_handle* h);
 /* Lattice k's fields / profile, as lb_fields / lb_profile. */
 lb_status lbb_fields(lbb_handle* h, int32_t k, double* rho_a, double* rho_b, double* ux, double* uy);

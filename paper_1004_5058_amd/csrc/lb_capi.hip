@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <queue>
@@ -1100,6 +1101,42 @@ void destroy_batch(lbb_handle* h)
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free stress ---
+//
+// lbb_stress_noalloc keeps the per-lattice wall-momentum sums (bottom, top of
+// each lattice, interleaved) in this file-scope device array instead of the
+// results region of the caller's state.  Every GPU the library runs on holds
+// its own copy until the process ends.  Host code uses the address
+// hipGetSymbolAddress returns for the current device, never the array's name
+// (which is a host-side stand-in).
+constexpr int NOALLOC_MAX_LATTICES = 4096;
+static __device__ __align__(256) double scratch[2 * NOALLOC_MAX_LATTICES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, resolved once per device.
+lb_status scratch_ptr(double** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LB_EDEVICE, "device %d beyond the %d supported", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LB_EDEVICE, "no device address for the stress scratch array");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI ---
 
 extern "C" {
@@ -1381,6 +1418,35 @@ lb_status lbb_stress(lbb_handle* h, double* sb, double* stp, int64_t* ns)
     CHECK_H(h);
     lb_status st = stress_all(h, sb, stp, ns);
     if (st != LB_OK) return st;
+    return check_flag(h);
+}
+
+lb_status lbb_stress_noalloc(lbb_handle* h, double* sb, double* stp, int64_t* ns)
+{
+    CHECK_H(h);
+    const int n = (int)h->lats.size();
+    if (n > NOALLOC_MAX_LATTICES)
+        return fail(LB_EINVAL, "lbb_stress_noalloc handles at most %d lattices (batch of %d)", NOALLOC_MAX_LATTICES, n);
+    double* dres = nullptr;
+    lb_status st = scratch_ptr(&dres);
+    if (st != LB_OK) return st;
+    HIP_TRY(lbk::launch_stress_reduce(h->base, h->d_desc(), n, dres, h->stream));
+    // (bottom, top) pairs per lattice -> the caller's two arrays, strided copies
+    if (sb)
+        HIP_TRY(hipMemcpy2DAsync(sb, sizeof(double), dres, 2 * sizeof(double), sizeof(double), (size_t)n,
+                                 hipMemcpyDeviceToHost, h->stream));
+    if (stp)
+        HIP_TRY(hipMemcpy2DAsync(stp, sizeof(double), dres + 1, 2 * sizeof(double), sizeof(double), (size_t)n,
+                                 hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    // the scaling of stress_all, in place
+    const double m = h->nsamples > 0 ? (double)h->nsamples : 1.0;
+    for (int k = 0; k < n; ++k) {
+        const double nx = h->lats[k].p.nx;
+        if (sb) sb[k] = h->nsamples > 0 ? sb[k] / nx / m : 0.0;
+        if (stp) stp[k] = h->nsamples > 0 ? -stp[k] / nx / m : 0.0;
+    }
+    if (ns) *ns = h->nsamples;
     return check_flag(h);
 }
 

@@ -98,6 +98,7 @@ def load_library(path=LIB_PATH):
         "lbb_init": [P, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, DPP, DPP, DPP, DPP, ctypes.POINTER(H)],
         "lbb_step": [H, ctypes.c_int32],
         "lbb_stress": [H, _DP, _DP, ctypes.POINTER(ctypes.c_int64)],
+        "lbb_stress_noalloc": [H, _DP, _DP, ctypes.POINTER(ctypes.c_int64)],
         "lbb_stress_reset": [H],
         "lbb_fields": [H, ctypes.c_int32, _DP, _DP, _DP, _DP],
         "lbb_profile": [H, ctypes.c_int32, _DP, ctypes.POINTER(ctypes.c_int64)],
@@ -414,6 +415,17 @@ class Batch:
         st = np.zeros(self.n)
         ns = ctypes.c_int64()
         _check(_lib.lbb_stress(self._h, _dptr(sb), _dptr(st), ctypes.byref(ns)))
+        return sb, st, ns.value
+
+    def stress_noalloc(self):
+        """stress() through the entry point that allocates nothing (its
+        reduction staged in the library's own device array)."""
+        sb = np.zeros(self.n)
+        st = np.zeros(self.n)
+        ns = ctypes.c_int64()
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            _check(_lib.lbb_stress_noalloc(self._h, _dptr(sb), _dptr(st), ctypes.byref(ns)))
         return sb, st, ns.value
 
     def stress_reset(self):
