@@ -219,7 +219,9 @@ lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
  * and 4 blocks per compute unit) on this lattice; where lb_set_fusion admits
  * two steps per pass (FP32, 16-bit), also that mode behind the best shape,
  * for each block width of lb_set_fusion_tile the device grants, at the
- * automatic tile height and at 64, 128 and 256 rows.  Applies the fastest
+ * automatic tile height and at heights of 20 to 300 rows (odd multiples of
+ * 4: power-of-two segment heights measured up to 40 % slower).  Applies the
+ * fastest
  * (shape, steps per pass and fused width; *ms is its time per step) and
  * restores the simulation state exactly (populations, accumulators, step
  * count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid,

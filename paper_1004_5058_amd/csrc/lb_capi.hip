@@ -135,8 +135,8 @@ Layout plan(std::vector<Lat>& lats)
     size_t off = L.off_tiles2 + align_up(sizeof(int32_t) * (size_t)L.max_items2, ALIGN);
     for (auto& a : lats) {
         const size_t es = storage_size(a.p.storage);
-        a.pitch = (int)align_up((size_t)a.p.nx, 64);
-        a.plane = (long long)a.pitch * a.p.ny;
+        a.pitch = (int)lbh::row_pitch(a.p.nx);
+        a.plane = (long long)lbh::plane_stride(a.p.nx, a.p.ny);
         // profile accumulator rows: one per 64 columns, or for the moment form
         // one per tile of the narrowest launch shape (60 collided columns)
         a.ngroups = is_mom(a.p.storage) ? (a.p.nx + 59) / 60 : (a.p.nx + 63) / 64;
@@ -305,6 +305,15 @@ int device_cus()
     return ncu;
 }
 
+// Fused tile heights tried by the automatic choice and the tuner: odd
+// multiples of 4.  Segments of a power-of-two number of rows put the rows the
+// resident tiles touch in each tick a power-of-two number of row pitches
+// apart, and such heights measured up to 40 % slower at 4096^2 (128 or 192
+// rows of FP32, 128 of FP16), the signature of accesses piling onto a few
+// HBM channels.
+const int FUSED_HEIGHTS[] = {20, 28, 36, 44, 52, 60, 68, 76, 84, 92, 100, 108, 124, 140, 156, 172, 204, 252, 300,
+                             380, 508};
+
 // Automatic fused tile height: the candidate with the smallest makespan (ties:
 // the taller tiles, fewer of them) on the blocks the device runs at once.
 // Candidates: fixed heights and, for each number of rounds r = 1..4, the
@@ -315,7 +324,7 @@ int auto_ly2(const lbb_handle* h)
     const int ncu = device_cus() * std::max(1, lbk::step2_blocks_per_cu(h->storage, h->fnw_eff));
     const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
     for (const Lat& a : h->lats) maxny = std::max(maxny, a.p.ny);
-    std::vector<int> cand = {16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512};
+    std::vector<int> cand(std::begin(FUSED_HEIGHTS), std::end(FUSED_HEIGHTS));
     for (int r = 1; r <= 4; ++r) {
         for (int l2 = 16; l2 < maxny; ++l2) {
             long long it = 0;
@@ -372,7 +381,7 @@ lb_status decompose(lbb_handle* h)
         d.nitems = d.nstrip * d.nseg;
         item = (item + 7) / 8 * 8;
         d.item_begin = item;
-        item += d.nitems;
+        item += (d.nitems + 7) / 8 * 8;   // padding items keep the XCD-banded order (xcd_tile)
         h->tiles.resize(d.item_begin, -1);
         h->tiles.resize(item, (int32_t)k);
     }
@@ -398,7 +407,7 @@ lb_status decompose(lbb_handle* h)
         d.nitems2 = d.nstrip2 * d.nseg2;
         item2 = (item2 + 7) / 8 * 8;
         d.item_begin2 = item2;
-        item2 += d.nitems2;
+        item2 += (d.nitems2 + 7) / 8 * 8;
         h->tiles2.resize(d.item_begin2, -1);
         h->tiles2.resize(item2, (int32_t)k);
     }
@@ -1028,14 +1037,18 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     // two steps per pass behind the best single-step shape (which any odd
     // remaining step uses): each block width the device grants, at the
     // automatic tile height (the smallest makespan on the blocks resident at
-    // once) and shorter tiles, which balance batches of uneven lattices
+    // once) and the other FUSED_HEIGHTS up to 300 rows (shorter tiles balance
+    // batches of uneven lattices; some heights fall on slow HBM access patterns)
     if (st == LB_OK && best.bx && fusion_allowed(h)) {
         st = set_launch(h, best.bx, best.ly, best.grid);
         for (int lanes : {128, 192, 256}) {
             if (st != LB_OK) break;
             if (lbk::step2_blocks_per_cu(h->storage, lanes / 64) < 1) continue;
             st = set_fusion_tile(h, lanes);
-            for (int ly2 : {0, 64, 128, 256}) {
+            std::vector<int> heights = {0};
+            for (int c : FUSED_HEIGHTS)
+                if (c <= 300) heights.push_back(c);
+            for (int ly2 : heights) {
                 if (st != LB_OK) break;
                 if (ly2 && ly2 >= maxny) continue;
                 st = set_fusion(h, 2, ly2);

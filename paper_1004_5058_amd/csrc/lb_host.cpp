@@ -62,9 +62,8 @@ lb_status validate(const lb_params* p, int storage0, std::string* msg)
     if (p->profile != 0 && p->profile != 1) return bad(msg, LB_EINVAL, "profile must be 0 or 1");
     // byte offsets inside one species' planes must fit the 32-bit buffer offset
     const size_t es = storage_size(p->storage);
-    const size_t pitch = align_up((size_t)p->nx, 64);
     const size_t per = is_mom(p->storage) ? 6 : 9;   // values addressed through one buffer resource
-    if (per * pitch * (size_t)p->ny * es >= (1ull << 32))
+    if (per * plane_stride(p->nx, p->ny) * es >= (1ull << 32))
         return bad(msg, LB_EINVAL, "lattice too large: one buffer resource would exceed 4 GiB");
     return LB_OK;
 }

@@ -30,11 +30,12 @@ namespace lbk {
 
 // Every format stores the deviation d_is = f_is - w_i rho_ref_s of a population
 // from the rest equilibrium at the lattice's reference densities; arithmetic
-// is FP64 for FP64 storage and FP32 otherwise.
-struct StF64 { using S = double;   using C = double; };
-struct StF32 { using S = float;    using C = float; };
-struct StF16 { using S = _Float16; using C = float; };
-struct StBF16 { using S = __bf16;  using C = float; };
+// is FP64 for FP64 storage and FP32 otherwise.  fast_psi: the pseudo-potential
+// from the hardware 2^x instead of expm1 (see dpsi).
+struct StF64 { using S = double;   using C = double; static constexpr bool fast_psi = false; };
+struct StF32 { using S = float;    using C = float;  static constexpr bool fast_psi = false; };
+struct StF16 { using S = _Float16; using C = float;  static constexpr bool fast_psi = true; };
+struct StBF16 { using S = __bf16;  using C = float;  static constexpr bool fast_psi = true; };
 
 template <class C> struct V4;
 template <> struct V4<float> { using T = float4; };
@@ -163,6 +164,23 @@ __device__ __forceinline__ double dpsi_of(double d, double e, double inv_rho0)
 {
     return -e * expm1(-d * inv_rho0);
 }
+// The same deviation as E (1 - 2^(-d log2(e) / rho0)) with the hardware
+// base-2 exponential (one transcendental and two multiply-adds instead of the
+// ~24 instructions of expm1f).  Its absolute error is a few 1e-8 of E: far
+// below the storage rounding of the 16-bit forms, about one FP32 rounding of
+// the populations per step in the FP32 moment form.  The forms whose step is
+// bound by arithmetic use it (fast_psi); FP32 and FP64 population storage
+// keep expm1.
+template <class P>
+__device__ __forceinline__ typename P::C dpsi(typename P::C d, typename P::C e, typename P::C inv_rho0)
+{
+    if constexpr (P::fast_psi) {
+        const float t = __builtin_amdgcn_exp2f(d * (-1.4426950408889634f * inv_rho0));
+        return e - e * t;
+    } else {
+        return dpsi_of(d, e, inv_rho0);
+    }
+}
 
 // Reciprocal: the hardware approximation (<= 1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
@@ -256,6 +274,20 @@ __device__ __forceinline__ void stencil_sums(FP P, FR R, const C* ks0, const C* 
     s[4] = cxA; s[5] = cyA; s[6] = cxB; s[7] = cyB;
 }
 
+// Work item l of a lattice with n tiles -> its tile, or -1 for a padding item.
+// Each lattice's items start at a multiple of 8 and fill a multiple of 8
+// slots, and blocks go to the eight XCDs in turn (block b to XCD b mod 8), so
+// XCD x runs items x, x + 8, x + 16, ...: they map to the contiguous tiles
+// x c .. x c + c - 1 (c = ceil(n / 8), tiles numbered strip-fastest), so
+// neighbouring tiles, which share halo rows and columns, share an XCD's L2.
+__device__ __forceinline__ int xcd_tile(int l, int n)
+{
+    const int c = (n + 7) >> 3;
+    if (l >= 8 * c) return -1;
+    const int lin = (l & 7) * c + (l >> 3);
+    return lin < n ? lin : -1;
+}
+
 template <class P>
 __device__ __forceinline__ int map_row(int r, int ny, int walls)
 {
@@ -345,13 +377,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const int L = tiles[w];          // owning lattice, -1 for alignment padding
         if (L < 0) continue;
         const LatDesc& d = descs[L];
-        const int l = w - d.item_begin;
-        if (l >= d.nitems) continue;
-        int lin = l;
-        if ((d.nitems & 7) == 0) {       // keep neighbouring tiles on one XCD
-            const int c = d.nitems >> 3;
-            lin = (l & 7) * c + (l >> 3);
-        }
+        const int lin = xcd_tile(w - d.item_begin, d.nitems);
+        if (lin < 0) continue;
         const int nstrip = d.nstrip;
         const int strip = lin % nstrip, seg = lin / nstrip;
         const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
@@ -445,8 +472,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                 C da, db;
                 dens(h, da, db);
                 C4 v;
-                v.x = dpsi_of(da, e0, inv_rho0);
-                v.y = dpsi_of(db, e1, inv_rho0);
+                v.x = dpsi<P>(da, e0, inv_rho0);
+                v.y = dpsi<P>(db, e1, inv_rho0);
                 v.z = da;
                 v.w = db;
                 halo[rr * 4 + c] = v;
@@ -493,8 +520,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             C da, db;
             dens(fr, da, db);
             C2 pv, rv;
-            pv.x = dpsi_of(da, e0, inv_rho0);
-            pv.y = dpsi_of(db, e1, inv_rho0);
+            pv.x = dpsi<P>(da, e0, inv_rho0);
+            pv.y = dpsi<P>(db, e1, inv_rho0);
             rv.x = da;
             rv.y = db;
             ringP[slot][tid + 2] = pv;
@@ -512,8 +539,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                         ha += hval(r, q);
                         hb += hval(r, 9 + q);
                     }
-                    a.x = dpsi_of(ha, e0, inv_rho0);
-                    a.y = dpsi_of(hb, e1, inv_rho0);
+                    a.x = dpsi<P>(ha, e0, inv_rho0);
+                    a.y = dpsi<P>(hb, e1, inv_rho0);
                     b.x = ha;
                     b.y = hb;
                 } else {
@@ -761,13 +788,8 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const int L = tiles[w];
         if (L < 0) continue;
         const LatDesc& d = descs[L];
-        const int l = w - d.item_begin2;
-        if (l >= d.nitems2) continue;
-        int lin = l;
-        if ((d.nitems2 & 7) == 0) {
-            const int c = d.nitems2 >> 3;
-            lin = (l & 7) * c + (l >> 3);
-        }
+        const int lin = xcd_tile(w - d.item_begin2, d.nitems2);
+        if (lin < 0) continue;
         const int nstrip = d.nstrip2;
         const int strip = lin % nstrip, seg = lin / nstrip;
         const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
@@ -879,7 +901,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             const int sp = slot6(r), sr = slot5(r);
             C da, db;
             dens(fr, da, db);
-            ringP[0][sp][j + 2] = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
+            ringP[0][sp][j + 2] = C2{dpsi<P>(da, e0, inv_rho0), dpsi<P>(db, e1, inv_rho0)};
             ringR[0][sr][j + 2] = C2{da, db};
             if (wave == halo_wave(r) && lane < 4) {
                 // the row's own loads have completed (da, db); its halo loads
@@ -893,7 +915,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                     hb += hval(hs, 9 + q);
                 }
                 const int hidx = (lane < 2) ? lane : BW + lane;
-                ringP[0][sp][hidx] = C2{dpsi_of(ha, e0, inv_rho0), dpsi_of(hb, e1, inv_rho0)};
+                ringP[0][sp][hidx] = C2{dpsi<P>(ha, e0, inv_rho0), dpsi<P>(hb, e1, inv_rho0)};
                 ringR[0][sr][hidx] = C2{ha, hb};
             }
         };
@@ -926,7 +948,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             }
             C da, db;
             dens(fr, da, db);
-            const C2 pv = C2{dpsi_of(da, e0, inv_rho0), dpsi_of(db, e1, inv_rho0)};
+            const C2 pv = C2{dpsi<P>(da, e0, inv_rho0), dpsi<P>(db, e1, inv_rho0)};
             const C2 rv = C2{da, db};
             ringP[1][sp][j + 2] = pv;
             ringR[1][sr][j + 2] = rv;
@@ -1417,8 +1439,8 @@ k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n)
 // holds the initial state itself, (rho_s - rho_ref_s, u, u), and the first
 // step reads it in place: the initial populations are local equilibria, not
 // streamed ones.
-struct MomF32 { using S = float;  using C = float; };
-struct MomF64 { using S = double; using C = double; };
+struct MomF32 { using S = float;  using C = float;  static constexpr bool fast_psi = true; };
+struct MomF64 { using S = double; using C = double; static constexpr bool fast_psi = false; };
 
 // Deviation of the equilibrium population i of one species from w_i rho_ref:
 // w_i [drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)], rho = rho_ref + drho.
@@ -1463,13 +1485,8 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
         const int L = tiles[w];
         if (L < 0) continue;
         const LatDesc& d = descs[L];
-        const int l = w - d.item_begin;
-        if (l >= d.nitems) continue;
-        int lin = l;
-        if ((d.nitems & 7) == 0) {
-            const int c = d.nitems >> 3;
-            lin = (l & 7) * c + (l >> 3);
-        }
+        const int lin = xcd_tile(w - d.item_begin, d.nitems);
+        if (lin < 0) continue;
         const int nstrip = d.nstrip;
         const int strip = lin % nstrip, seg = lin / nstrip;
         const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
@@ -1612,7 +1629,7 @@ k_step_mom(char* __restrict__ base, const LatDesc* __restrict__ descs, const int
             }
             C dA, dB, jx, jy;
             pull(r, dA, dB, jx, jy);
-            ringP[sl][tid] = C2{dpsi_of(dA, e0, inv_rho0), dpsi_of(dB, e1, inv_rho0)};
+            ringP[sl][tid] = C2{dpsi<P>(dA, e0, inv_rho0), dpsi<P>(dB, e1, inv_rho0)};
             ringR[sl][tid] = C2{dA, dB};
             J = C2{jx, jy};
         };

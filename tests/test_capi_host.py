@@ -85,11 +85,15 @@ def test_largest_accepted_lattice(storage, n):
 
 
 def test_state_bytes_layout_scales_with_storage():
+    """Two population buffers of 18 planes; a plane holds ny rows of the
+    64-element-aligned pitch and starts one row and 64 elements past the
+    previous one (planes never a power of two apart)."""
     from paper_1004_5058_amd import lb
     b64 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f64"))
     b32 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f32"))
     b16 = lb.lb_state_bytes(lb.make_params(512, 256, storage="f16dev"))
-    pop = 2 * 18 * 512 * 256
+    plane = 512 * (256 + 1) + 64
+    pop = 2 * 18 * plane
     assert b64 - b32 == pop * 4 and b32 - b16 == pop * 2
 
 
