@@ -11,17 +11,25 @@ step t's populations on chip and runs step t+1 behind it, bitwise the result
 of single steps, so each population crosses HBM once per two updates); the
 single-step kernel ("f32"), FP16- and BF16-deviation storage and the moment
 form ("mom32": at tau = 1 six moments per site, 48 bytes per update) are timed
-beside it.  Each variant's `frac` uses the algorithmic bytes of one update in
-its storage (144 for FP32); f32x2 also reports its own floor (72 B per update).
-The roofline object is the headline variant's.
+beside it.  Each variant's `frac` is the HBM floor of its launches (each
+population or moment read once and written once per launch: 144 B per update
+for FP32 one step per pass, 72 B two steps per pass) over the launch time;
+`effective_gbs` states the one-step bytes (144 B for FP32) at the same
+throughput.  The roofline object is the headline variant's.
 
-Prints one JSON line.  `roofline.achieved` is the algorithmic HBM traffic of a
-step (18 population loads + 18 stores per site) divided by the device time per
-step, from HIP events recorded on the lattice's stream around the timed steps.  `hbm` adds
-the rate of the measured traffic (rocprofv3 counters, when taken on the
-current kernel source) and the live rate of a plain streaming copy on the same
-GPU.  `cpu_baseline` is the FP64 oracle on all host threads, with a
-single-thread rate beside it.
+Prints one JSON line.  `roofline.achieved` is the floor bytes of one launch
+divided by the device time per launch, from HIP events recorded on the
+lattice's stream around the timed steps; `roofline.traffic` is the HBM bytes
+of a launch that rocprofv3's FETCH_SIZE / WRITE_SIZE counters measured on the
+current kernel source (null once the source has changed).  `hbm` adds the rate
+of that traffic and the live rate of a plain streaming copy on the same GPU.
+Each variant carries its error against the FP64 step at the benchmark's own
+length and the record of the 5000-step workload length.  `cpu_baseline` is
+the FP64 oracle on all host threads, with a single-thread rate beside it.
+
+Before each variant's warm-up, the same step kernel runs for half a second on
+a separate lattice of the same size and storage (clock ramp): the first tens
+of launches after a second of idle GPU run 3-15 % slow.
 
 The launch shape comes from the project's autotuner (timed before the timed
 region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
@@ -32,8 +40,8 @@ With --knee, a network trained on 2000 ensemble lattices proposes flow-curve
 refinements near the yield stress, each checked by a 1024x512 lattice run.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--variants f32x2,f32,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve] [--no-tune]
-       [--no-surrogate] [--knee]
+       [--variants f32x2,f32,f16x2,bf16x2,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve]
+       [--no-tune] [--no-surrogate] [--no-errors] [--ramp SECONDS] [--knee]
 """
 import argparse
 import hashlib
@@ -227,7 +235,7 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     b = lb.Batch(specs, storage="f32", profile=True)
     if tune_cache is not None:
         # tuned before the timed run; the run applies the cached entry
-        b.autotune(tune_cache, steps=3)
+        b.autotune(tune_cache, steps=10)
     shape = b.launch()
     b.close()
     rows_b, wall_b = flowcurve.run_batched(specs, steps, tune_cache=tune_cache)
@@ -238,7 +246,7 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
     # the same ensemble in the moment form (tau = 1), batched, tuned shape
     b = lb.Batch(specs, storage="mom32", profile=True)
     if tune_cache is not None:
-        b.autotune(tune_cache, steps=3)
+        b.autotune(tune_cache, steps=10)
     tm = b.launch()
     b.close()
     rows_m, wall_m = flowcurve.run_batched(specs, steps, storage="mom32", tune_cache=tune_cache)
@@ -516,9 +524,12 @@ def main():
     if a.knee:
         from paper_1004_5058_amd import surrogate
         try:
-            line["knee_refinement"] = surrogate.knee_refinement(
+            kr = surrogate.knee_refinement(
                 couplings=((-9.0, 8.1), (-9.2, 8.0), (-8.8, 7.7)),
                 log=lambda m: print(f"# knee refinement: {m}", file=sys.stderr, flush=True))
+            for c in kr["curves"]:
+                c.pop("network_curve", None)      # 400 samples per curve: not for the one-line record
+            line["knee_refinement"] = kr
         except Exception as e:  # reported, never hidden
             line["knee_refinement"] = {"error": repr(e)}
     if not a.no_cpu:

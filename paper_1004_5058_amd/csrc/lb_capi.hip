@@ -274,20 +274,44 @@ void drop_graphs(lbb_handle* h)
         if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
 }
 
-// Makespan, in ticks, of the fused tiles of height ly2 listed lattice by
-// lattice and scheduled greedily on `slots` concurrent blocks.
+// Rows of the tallest fused segment of a lattice of ny rows at tile height ly2.
+int fused_height(int ny, int ly2)
+{
+    const int n = lbh::fused_nseg(ny, ly2);
+    return (ny + n - 1) / n;
+}
+
+// Order in which the lattices' fused tiles are handed out: by segment height,
+// tallest first (stable), so the short tiles of shallow lattices fill the end
+// of the schedule (longest processing time first; every tile of a lattice has
+// the same height to a row).
+std::vector<int> fused_order(const lbb_handle* h, int ly2)
+{
+    std::vector<int> ord(h->lats.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return fused_height(h->lats[a].p.ny, ly2) > fused_height(h->lats[b].p.ny, ly2);
+    });
+    return ord;
+}
+
+// Makespan, in ticks, of the fused tiles of height at most ly2 (each lattice's
+// rows split into fused_nseg near-equal segments, as the kernel does), handed
+// out in fused_order and scheduled greedily on `slots` concurrent blocks; a
+// tile of h rows costs h + 8 ticks (the overlap rows of the two steps).
 long long fused_makespan(const lbb_handle* h, int ly2, int slots)
 {
     std::priority_queue<long long, std::vector<long long>, std::greater<long long>> free_at;
     for (int c = 0; c < slots; ++c) free_at.push(0);
     long long end = 0;
     const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
-    for (const Lat& a : h->lats) {
+    for (int k : fused_order(h, ly2)) {
+        const Lat& a = h->lats[k];
         const int strips = (a.p.nx + tw - 1) / tw;
-        const int lh = std::min(ly2, a.p.ny);
+        const int nseg = lbh::fused_nseg(a.p.ny, ly2), sb = a.p.ny / nseg, sx = a.p.ny - sb * nseg;
         for (int st = 0; st < strips; ++st)
-            for (int y = 0; y < a.p.ny; y += lh) {
-                const long long t = free_at.top() + std::min(lh, a.p.ny - y) + 8;
+            for (int g = 0; g < nseg; ++g) {
+                const long long t = free_at.top() + sb + (g < sx ? 1 : 0) + 8;
                 free_at.pop();
                 free_at.push(t);
                 end = std::max(end, t);
@@ -314,32 +338,27 @@ int device_cus()
 const int FUSED_HEIGHTS[] = {20, 28, 36, 44, 52, 60, 68, 76, 84, 92, 100, 108, 124, 140, 156, 172, 204, 252, 300,
                              380, 508};
 
-// Automatic fused tile height: the candidate with the smallest makespan (ties:
+// Automatic fused tile height: the height with the smallest makespan (ties:
 // the taller tiles, fewer of them) on the blocks the device runs at once.
-// Candidates: fixed heights and, for each number of rounds r = 1..4, the
-// smallest height whose tiles fit r rounds.
+// Candidates: every height up to 64 rows, then heights about 1.5 % apart up to
+// the tallest lattice, among those whose tiles fill at most 16 rounds of the
+// device's blocks (more rounds leave a negligible tail; the tallest candidate
+// is always kept).
 int auto_ly2(const lbb_handle* h)
 {
     int maxny = 1;
-    const int ncu = device_cus() * std::max(1, lbk::step2_blocks_per_cu(h->storage, h->fnw_eff));
+    const int slots = device_cus() * std::max(1, lbk::step2_blocks_per_cu(h->storage, h->fnw_eff));
     const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
     for (const Lat& a : h->lats) maxny = std::max(maxny, a.p.ny);
-    std::vector<int> cand(std::begin(FUSED_HEIGHTS), std::end(FUSED_HEIGHTS));
-    for (int r = 1; r <= 4; ++r) {
-        for (int l2 = 16; l2 < maxny; ++l2) {
-            long long it = 0;
-            for (const Lat& a : h->lats)
-                it += (long long)((a.p.nx + tw - 1) / tw) * ((a.p.ny + l2 - 1) / l2);
-            if (it <= (long long)r * ncu) { cand.push_back(l2); break; }
-        }
-    }
-    cand.push_back(maxny);
     int best = maxny;
     long long best_t = -1;
-    for (int c : cand) {
-        if (c < 1 || c > maxny) continue;
-        const long long t = fused_makespan(h, c, ncu);
-        if (best_t < 0 || t < best_t || (t == best_t && c > best)) { best_t = t; best = c; }
+    for (int c = maxny; c >= 1; c -= (c > 64 ? std::max(1, c / 64) : 1)) {
+        long long tiles = 0;
+        for (const Lat& a : h->lats)
+            tiles += (long long)((a.p.nx + tw - 1) / tw) * lbh::fused_nseg(a.p.ny, c);
+        if (c < maxny && tiles > 16LL * slots) break;   // shorter heights only add tiles
+        const long long t = fused_makespan(h, c, slots);
+        if (best_t < 0 || t < best_t) { best_t = t; best = c; }
     }
     return best;
 }
@@ -398,12 +417,12 @@ lb_status decompose(lbb_handle* h)
     const int tw = lbk::fuse2_tw(h->storage, h->fnw_eff);
     int item2 = 0;
     h->tiles2.clear();
-    for (size_t k = 0; k < h->lats.size(); ++k) {
+    for (int k : fused_order(h, ly2)) {
         const Lat& a = h->lats[k];
         lbk::LatDesc& d = h->descs[k];
         d.nstrip2 = (a.p.nx + tw - 1) / tw;
-        d.ly2 = std::min(ly2, a.p.ny);
-        d.nseg2 = (a.p.ny + d.ly2 - 1) / d.ly2;
+        d.nseg2 = lbh::fused_nseg(a.p.ny, ly2);
+        d.ly2 = (a.p.ny + d.nseg2 - 1) / d.nseg2;   // the tallest segment
         d.nitems2 = d.nstrip2 * d.nseg2;
         item2 = (item2 + 7) / 8 * 8;
         d.item_begin2 = item2;
@@ -1010,9 +1029,35 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         ncu = prop.multiProcessorCount;
-    TuneEntry best;
+    // Candidates are timed in two rounds: every shape once over `steps`
+    // steps, then the fastest few again, twice, over 4 x steps (the best time
+    // of those runs decides).  A single short timing is noisy: the first tens
+    // of launches after an idle GPU run 3-15 % slow, so the device is first
+    // kept busy for about 0.3 s with the default shape.
+    std::vector<TuneEntry> cands;
     lb_status st = LB_OK;
+    {
+        double ms1 = 0;
+        st = steps_direct_warm(h, 2);
+        if (st == LB_OK) st = time_steps(h, 2, &ms1);
+        if (st == LB_OK && ms1 > 0) {
+            const int warm = (int)std::min(20000.0, 300.0 / ms1);
+            for (int done = 0; st == LB_OK && done < warm; done += 256)
+                st = steps_direct_warm(h, std::min(256, warm - done));
+        }
+    }
+    auto time_entry = [&](TuneEntry& e, int n) -> lb_status {
+        lb_status s2 = set_launch(h, e.bx, e.ly, e.grid);
+        if (s2 == LB_OK && e.fusion == 2) s2 = set_fusion_tile(h, e.fw);
+        if (s2 == LB_OK) s2 = set_fusion(h, e.fusion, e.fusion == 2 ? e.ly2 : 0);
+        if (s2 == LB_OK) s2 = steps_direct_warm(h, 2);
+        double ms = 0;
+        if (s2 == LB_OK) s2 = time_steps(h, n + (e.fusion == 2 ? (n & 1) : 0), &ms);
+        if (s2 == LB_OK) e.ms = ms;
+        return s2;
+    };
     for (int bx : {64, 128, 256, 512}) {
+        if (st != LB_OK) break;
         if (!bx_supported(h->storage, bx) || (bx > 64 && bx / 2 >= maxnx)) continue;
         for (int ly : {8, 16, 32, 48, 64, 80, 96, 128, 160, 192, 256}) {
             if (ly > 16 && ly / 2 >= maxny) continue;
@@ -1021,50 +1066,56 @@ lb_status autotune(lbb_handle* h, const char* cache_path, int steps, bool batch,
             if (batch)
                 for (int per : {1, 2, 4}) grids.push_back(ncu * per);
             for (int grid : grids) {
-                st = set_launch(h, bx, ly, grid);
+                TuneEntry e;
+                e.bx = bx; e.ly = ly; e.grid = grid;
+                st = time_entry(e, steps);
                 if (st != LB_OK) break;
-                st = steps_direct_warm(h, 2);
-                if (st != LB_OK) break;
-                double ms = 0;
-                st = time_steps(h, steps, &ms);
-                if (st != LB_OK) break;
-                if (!best.bx || ms < best.ms) { best.bx = bx; best.ly = ly; best.grid = grid; best.ms = ms; }
+                cands.push_back(e);
             }
             if (st != LB_OK) break;
         }
-        if (st != LB_OK) break;
     }
     // two steps per pass behind the best single-step shape (which any odd
     // remaining step uses): each block width the device grants, at the
-    // automatic tile height (the smallest makespan on the blocks resident at
-    // once) and the other FUSED_HEIGHTS up to 300 rows (shorter tiles balance
-    // batches of uneven lattices; some heights fall on slow HBM access patterns)
-    if (st == LB_OK && best.bx && fusion_allowed(h)) {
-        st = set_launch(h, best.bx, best.ly, best.grid);
+    // automatic tile height (the smallest modelled makespan) and the other
+    // FUSED_HEIGHTS up to 300 rows (the model is approximate: measured times
+    // differ from it by several per cent)
+    TuneEntry best1;
+    for (const TuneEntry& e : cands)
+        if (!best1.bx || e.ms < best1.ms) best1 = e;
+    if (st == LB_OK && best1.bx && fusion_allowed(h)) {
         for (int lanes : {128, 192, 256}) {
             if (st != LB_OK) break;
             if (lbk::step2_blocks_per_cu(h->storage, lanes / 64) < 1) continue;
-            st = set_fusion_tile(h, lanes);
             std::vector<int> heights = {0};
             for (int c : FUSED_HEIGHTS)
                 if (c <= 300) heights.push_back(c);
             for (int ly2 : heights) {
                 if (st != LB_OK) break;
                 if (ly2 && ly2 >= maxny) continue;
-                st = set_fusion(h, 2, ly2);
-                if (st == LB_OK) st = steps_direct_warm(h, 2);
-                double ms = 0;
-                if (st == LB_OK) st = time_steps(h, steps + (steps & 1), &ms);
-                if (st == LB_OK && ms < best.ms) {
-                    best.fusion = 2;
-                    best.ly2 = ly2;
-                    best.fw = lanes;
-                    best.ms = ms;
-                }
+                TuneEntry e = best1;
+                e.fusion = 2; e.ly2 = ly2; e.fw = lanes;
+                st = time_entry(e, steps);
+                if (st == LB_OK) cands.push_back(e);
             }
         }
-        h->fusion = 1;
     }
+    TuneEntry best;
+    if (st == LB_OK && !cands.empty()) {
+        std::stable_sort(cands.begin(), cands.end(), [](const TuneEntry& x, const TuneEntry& y) { return x.ms < y.ms; });
+        const size_t nf = std::min<size_t>(cands.size(), 4);
+        for (size_t i = 0; i < nf && st == LB_OK; ++i) {
+            TuneEntry e = cands[i];
+            double m = 1e300;
+            for (int r = 0; r < 2 && st == LB_OK; ++r) {
+                st = time_entry(e, 4 * steps);
+                m = std::min(m, e.ms);
+            }
+            e.ms = m;
+            if (st == LB_OK && (!best.bx || e.ms < best.ms)) best = e;
+        }
+    }
+    h->fusion = 1;
     // restore the state
     o = 0;
     h->cur = cur;

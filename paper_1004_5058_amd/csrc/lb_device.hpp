@@ -23,8 +23,10 @@ struct LatDesc {
     int ngroups;           // ceil(nx / 64) (moment form: ceil(nx / 60))
     int ngroups2;          // partial sums of the fused two-step kernel, 2 steps x nstrip2 x waves per step
                            // (rows reserved for its widest layout; 0: no fused kernel for the storage)
-    // Tiles of the fused two-step kernel: strips of fuse2_tw columns, segments
-    // of ly2 rows, items item_begin2 .. item_begin2 + nitems2 - 1 of its own table.
+    // Tiles of the fused two-step kernel: strips of fuse2_tw columns, nseg2
+    // segments of near-equal height (ny / nseg2 rows, the first ny mod nseg2
+    // one row more; ly2 the tallest), items item_begin2 .. item_begin2 +
+    // nitems2 - 1 of its own table.
     int item_begin2, nitems2, nstrip2, nseg2, ly2;
     double tau, omega, rho0, inv_rho0;
     double ks[2][5];       // psi-stencil coefficient of species s on the shells |c|^2 = 1,2,4,5,8

@@ -193,6 +193,50 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// A 32-bit lane move by DPP control CTRL applied to both halves of an FP64
+// value (all 64 lanes active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The wave-wide sums of two vectors at once (FP64, all 64 lanes active),
+// without the LDS crossbar: the sum of d0 ends in lanes 0..31, of d1 in lanes
+// 32..63.  The gfx950 row swap v_permlane32_swap exchanges the upper half of
+// d0 with the lower half of d1, so one addition does the lane-distance-32
+// step of both; v_permlane16_swap then pairs 16-lane rows; the rest is the
+// xor butterfly over lane distances 1 and 2 (DPP quad permutations), then 4
+// and 8 (the half-row and row mirrors: after the first steps every lane of a
+// quad, then of an 8-lane group, holds the same value, so the mirror's
+// partner holds what the xor partner holds).  About half the work of two
+// separate wave sums.
+__device__ __forceinline__ double wave_sum2_dpp(double d0, double d1)
+{
+    auto lo = [](double x) { return (unsigned)__builtin_bit_cast(unsigned long long, x); };
+    auto hi = [](double x) { return (unsigned)(__builtin_bit_cast(unsigned long long, x) >> 32); };
+    auto mk = [](unsigned l, unsigned h) { return __builtin_bit_cast(double, ((unsigned long long)h << 32) | l); };
+    // first result: d0's lower half, then d1's lower half moved up; second:
+    // d0's upper half moved down, then d1's upper half
+    const auto l32 = __builtin_amdgcn_permlane32_swap(lo(d0), lo(d1), false, false);
+    const auto h32 = __builtin_amdgcn_permlane32_swap(hi(d0), hi(d1), false, false);
+    double v = mk(l32[0], h32[0]) + mk(l32[1], h32[1]);
+    // with both operands v: the first result holds, in odd rows, the even row
+    // below; the second, in even rows, the odd row above
+    const auto l16 = __builtin_amdgcn_permlane16_swap(lo(v), lo(v), false, false);
+    const auto h16 = __builtin_amdgcn_permlane16_swap(hi(v), hi(v), false, false);
+    const bool odd = (__lane_id() >> 4) & 1;
+    v += odd ? mk(l16[0], h16[0]) : mk(l16[1], h16[1]);
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]: lane l^1
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lane l^2
+    v += dpp_move<0x141>(v);   // row_half_mirror: the other quad of the 8-lane group
+    v += dpp_move<0x140>(v);   // row_mirror: the other 8-lane group of the 16-lane row
+    return v;
+}
+
 // Force stencil sums of one site.  P(dy, dx) and R(dy, dx) return the staged
 // (species A, species B) psi and rho deviations of the neighbour at offset
 // (dx, dy).  Out: s[0..3] = x and y sums of the psi terms (A, then B) with
@@ -781,8 +825,10 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     const int j = tid - role * BW;
     const int wave = __builtin_amdgcn_readfirstlane(j >> 6), lane = tid & 63;
     // step t's per-row halo work rotates over its waves
-    auto halo_wave = [&](int r) { return ((r % NW) + NW) % NW; };
-    auto hslot = [&](int r) { return ((r % HS) + HS) % HS; };
+    // (rows reach down to y0 - 5 >= -5; 24 is a multiple of NW and HS, so the
+    // unsigned remainders are those of r)
+    auto halo_wave = [&](int r) { return (int)((unsigned)(r + 24) % (unsigned)NW); };
+    auto hslot = [&](int r) { return (int)((unsigned)(r + 24) % (unsigned)HS); };
 
     for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
         const int L = tiles[w];
@@ -795,8 +841,11 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
         const long long plane = d.plane;
         const int X = strip * TW;
-        const int y0 = seg * d.ly2;
-        const int y1 = min(y0 + d.ly2, ny);
+        // nseg2 segments of near-equal height: the first ny mod nseg2 of them
+        // one row taller (no short last segment)
+        const int sb = ny / d.nseg2, sx = ny - sb * d.nseg2;
+        const int y0 = seg * sb + min(seg, sx);
+        const int y1 = y0 + sb + (seg < sx ? 1 : 0);
         auto wrap = [&](int c) { c %= nx; return c < 0 ? c + nx : c; };
         const int x0 = X - XO;
         const unsigned xc = (unsigned)wrap(x0 + j);
@@ -844,7 +893,8 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         double* __restrict__ stress = (double*)(base + d.off_stress);
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
         // line profile: each wave adds the sum of u_x over its own columns of
-        // every collided row of this tile to its partial, per step
+        // every collided row of this tile to its partial, per step (state
+        // memory is ordinary device memory, where FP64 atomics are native)
         double* __restrict__ prof2 =
             d.off_prof >= 0 ? (double*)(base + d.off_prof) + (long long)d.ngroups * ny : nullptr;
         C mom_b = 0, mom_t = 0;
@@ -888,11 +938,14 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 return (C)__builtin_bit_cast(float, hst[hs][q][lane]);
             }
         };
-        auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 8) % 6); };
-        auto slot5 = [&](int r) { return __builtin_amdgcn_readfirstlane((r - y0 + 10) % 5); };
+        // ring slots: every row index here is >= y0 - 6, so the operands are
+        // non-negative and unsigned remainders (cheaper scalar code) are exact
+        auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((int)((unsigned)(r - y0 + 8) % 6u)); };
+        auto slot5 = [&](int r) { return __builtin_amdgcn_readfirstlane((int)((unsigned)(r - y0 + 10) % 5u)); };
         // ring row of population class c (pr_class) for row r
         auto prow = [&](int c, int r) {
-            return __builtin_amdgcn_readfirstlane(c == 0 ? (r & 3) : (c == 1 ? 4 + (r - y0 + 9) % 3 : 7 + (r & 1)));
+            return __builtin_amdgcn_readfirstlane(
+                c == 0 ? (r & 3) : (c == 1 ? 4 + (int)((unsigned)(r - y0 + 9) % 3u) : 7 + (r & 1)));
         };
 
         // Step t: stage row r (HBM populations in fr) into ring 0, plus the
@@ -960,7 +1013,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
 
         // Collide row y of step `k` (0: t, pushes into the LDS ring; 1: t+1,
         // stores to HBM).  The arithmetic is k_step's.
-        auto collide = [&](const R& f, int y, int k) {
+        auto collide = [&](const R& f, int y, int k, C& pu) {
             int sl[5], sr[5];
             sl[0] = slot6(y - 2);
             sr[0] = slot5(y - 2);
@@ -987,12 +1040,33 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                        + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
             const C inv_rho = rcp(ra + rb);
             const C ux = jx * inv_rho, uy = jy * inv_rho;
-            const int yw = ((y % ny) + ny) % ny;   // periodic image of a step-t row (any ny)
-            const C gx = (body != nullptr) ? (C)body[yw] * inv_rho : (C)0;
+            C gx = (C)0;
+            if (body != nullptr) {
+                const int yw = ((y % ny) + ny) % ny;   // periodic image of a step-t row (any ny)
+                gx = (C)body[yw] * inv_rho;
+            }
             if (prof2 != nullptr && y >= y0 && y < y1) {
-                double su = own ? (double)ux : 0.0;
-                su = wave_sum(su);
-                if (lane == 0) prof2[((long long)(k * nstrip + strip) * NW + wave) * ny + y] += su;
+                // line profile: rows y0, y0+1, ... are collided in consecutive
+                // ticks; the first row of each pair holds its own-column u_x
+                // in pu, the second sums both rows in one FP64 wave sum (a
+                // last unpaired row alone) and adds each row's sum to the
+                // wave's partial of (step, strip, wave, row).  Each partial
+                // gets one add per launch: a no-return atomic gives the
+                // read-modify-write without waiting for the read (which would
+                // also wait for every load issued before it, the next rows'
+                // populations); no other wave touches the address, so the
+                // result is deterministic.
+                const C cur = own ? ux : (C)0;
+                const bool second = ((y - y0) & 1) != 0;
+                if (!second && y + 1 < y1) {
+                    pu = cur;
+                } else {
+                    const double sum = second ? wave_sum2_dpp((double)pu, (double)cur)
+                                              : wave_sum2_dpp((double)cur, 0.0);
+                    const int yr = second ? y - 1 + (lane >> 5) : y;
+                    if ((lane & 31) == 0 && (second || lane == 0))
+                        unsafeAtomicAdd(&prof2[((long long)(k * nstrip + strip) * NW + wave) * ny + yr], sum);
+                }
             }
             const bool bot = walls && (y == 0);
             const bool top = walls && (y == ny - 1);
@@ -1119,7 +1193,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             stage1(F0, A0);
             stage1(F1, A0 + 1);
             const bool top_here = walls && ny - 1 >= A0 && ny - 1 < A1;
-            auto tick = [&](int a, const R& fc, const R& fs2, R& fl) {
+            auto tick = [&](int a, const R& fc, const R& fs2, R& fl, C& pu) {
                 if (a < A1) {
                     stage1(fs2, a + 2);
                     if (a + 3 <= A1 + 1) {
@@ -1128,32 +1202,34 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                     }
                 }
                 lds_barrier();
-                if (a < A1 && (!walls || (a >= 0 && a < ny))) collide(fc, a, 0);
+                if (a < A1 && (!walls || (a >= 0 && a < ny))) collide(fc, a, 0, pu);
                 if (top_here && a == ny) put_held();
             };
+            C pu = (C)0;
             for (int a = A0; a <= T1; a += 4) {
-                tick(a, F0, F2, F3);
-                if (a + 1 <= T1) tick(a + 1, F1, F3, F0);
-                if (a + 2 <= T1) tick(a + 2, F2, F0, F1);
-                if (a + 3 <= T1) tick(a + 3, F3, F1, F2);
+                tick(a, F0, F2, F3, pu);
+                if (a + 1 <= T1) tick(a + 1, F1, F3, F0, pu);
+                if (a + 2 <= T1) tick(a + 2, F2, F0, F1, pu);
+                if (a + 3 <= T1) tick(a + 3, F3, F1, F2, pu);
             }
         } else {
             // row a-3 is complete since tick a-2 and visible since the
             // previous barrier; staging it before this tick's barrier
             // balances the two halves (each: stage, barrier, collide).  The
             // row staged in tick a is collided in tick a+2.
-            auto tick = [&](int a, const R& fc, R& fs2) {
+            auto tick = [&](int a, const R& fc, R& fs2, C& pu) {
                 const int r = a - 3;
                 if (r >= y0 - 2 && r <= y1 + 1) stage2(fs2, r);
                 lds_barrier();
                 const int c = a - 5;
-                if (c >= y0 && c < y1) collide(fc, c, 1);
+                if (c >= y0 && c < y1) collide(fc, c, 1, pu);
             };
+            C pu = (C)0;
             for (int a = A0; a <= T1; a += 4) {
-                tick(a, F0, F2);
-                if (a + 1 <= T1) tick(a + 1, F1, F3);
-                if (a + 2 <= T1) tick(a + 2, F2, F0);
-                if (a + 3 <= T1) tick(a + 3, F3, F1);
+                tick(a, F0, F2, pu);
+                if (a + 1 <= T1) tick(a + 1, F1, F3, pu);
+                if (a + 2 <= T1) tick(a + 2, F2, F0, pu);
+                if (a + 3 <= T1) tick(a + 3, F3, F1, pu);
             }
         }
         // wall momentum in FP64, step t's first, then step t+1's (the order

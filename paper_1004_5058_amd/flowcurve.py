@@ -137,7 +137,7 @@ def run_batched(specs, steps, storage="f32", average_from=None, bx=0, ly=0, grid
     t0 = time.perf_counter()
     b = lb.Batch(specs, storage=storage, profile=True)
     if tune_cache is not None:
-        b.autotune(tune_cache, steps=3)
+        b.autotune(tune_cache, steps=10)
     elif bx or ly or grid:
         b.set_launch(bx, ly, grid)
     b.set_graph(graph)

@@ -164,13 +164,21 @@ def knee_refinement(n_train=2000, steps=10000, couplings=((-9.0, 8.1),), k=6, wi
     Sh = np.array([r["S"] for r in held])
     sh = np.array([r["sigma"] for r in held])
     e_held = np.abs(surr.predict(g1h, g2h, Sh) - sh) / np.maximum(np.abs(sh), 1e-300)
+    # the same error of the constant predictor (the training rows' median stress)
+    e_const = np.abs(np.median([r["sigma"] for r in train]) - sh) / np.maximum(np.abs(sh), 1e-300)
+    # the fit to the training rows in the network's own target space
+    yt = to_target([r["sigma"] for r in train])
+    pt = to_target(surr.predict(np.array([r["g_aa1"] for r in train]), np.array([r["g_aa2"] for r in train]),
+                                np.array([r["S"] for r in train])))
     S_all = np.array([r["S"] for r in rows])
     S_lo, S_hi = float(S_all.min()), float(S_all.max())
     curves, t_chk, accepted, total = [], 0.0, 0, 0
     for c, (g1, g2) in enumerate(couplings):
         S_prop, fit = surr.propose(g1, g2, S_lo, S_hi, k=k, width=width)
         pred = surr.predict(g1, g2, S_prop)
-        lb_rows, w = lb_flow_points(S_prop, g1, g2, steps, ny=check_ny, nx=check_nx, seed=seed + 10000 + 100 * c)
+        S_grid = np.logspace(np.log10(S_lo), np.log10(S_hi), 400)      # the curve knee() fits
+        check_seed = seed + 10000 + 100 * c
+        lb_rows, w = lb_flow_points(S_prop, g1, g2, steps, ny=check_ny, nx=check_nx, seed=check_seed)
         t_chk += w
         lbs = np.array([r["sigma"] for r in lb_rows])
         err = np.abs(pred - lbs) / np.maximum(np.abs(lbs), 1e-300)
@@ -180,7 +188,10 @@ def knee_refinement(n_train=2000, steps=10000, couplings=((-9.0, 8.1),), k=6, wi
         curves.append(dict(g_aa1=g1, g_aa2=g2, knee_S=float(surr.knee(g1, g2, S_lo, S_hi)[0]),
                            hb_network=fit, S=[float(x) for x in S_prop], sigma_network=[float(x) for x in pred],
                            sigma_lattice=[float(x) for x in lbs], rel_err=[float(x) for x in err],
-                           accepted=ok, hb_lattice=flowcurve.hb_fit(S_prop, lbs) if len(S_prop) >= 3 else None))
+                           accepted=ok, hb_lattice=flowcurve.hb_fit(S_prop, lbs) if len(S_prop) >= 3 else None,
+                           check_seed=check_seed,
+                           network_curve=dict(S=[float(x) for x in S_grid],
+                                              sigma=[float(x) for x in surr.predict(g1, g2, S_grid)])))
         if log:
             log(f"coupling ({g1}, {g2}): knee {curves[-1]['knee_S']:.3e}, errors "
                 + ", ".join(f"{x:.3f}" for x in err))
@@ -188,6 +199,8 @@ def knee_refinement(n_train=2000, steps=10000, couplings=((-9.0, 8.1),), k=6, wi
     return dict(train_lattices=len(train), held_out=len(held), steps=steps, train_storage=train_storage,
                 check_lattice=f"{check_nx}x{check_ny}", S_range=[S_lo, S_hi], train_loss=float(loss),
                 held_out_rel_err_median=float(np.median(e_held)), held_out_rel_err_p90=float(np.quantile(e_held, 0.9)),
+                held_out_rel_err_const_median=float(np.median(e_const)),
+                train_target_mse=float(np.mean((pt - yt) ** 2)), train_target_var=float(np.var(yt)),
                 ensemble_s=round(t_ens, 2), train_s=round(t_fit, 2), check_s=round(t_chk, 2), wall_s=round(wall, 2),
                 proposals=total, accepted=accepted, points_per_hour=round(accepted * 3600.0 / wall, 1),
                 curves=curves)

@@ -183,8 +183,28 @@ static void test_checkpoint()
     }
 }
 
+// Fused segments: every tile at most ly2 rows (ly2 >= 1), at least ceil(ny / ly2)
+// segments, never more segments than rows, and no equal split into a multiple
+// of 16 rows while a finer split exists.
+static void test_fused_segments()
+{
+    for (int ny = 1; ny <= 1100; ++ny)
+        for (int ly2 = 1; ly2 <= ny + 3; ly2 += (ly2 < 40 ? 1 : 7)) {
+            const int n = lbh::fused_nseg(ny, ly2);
+            EXPECT(n >= 1 && n <= ny);
+            EXPECT(n >= (ny + ly2 - 1) / ly2 || ly2 > ny);
+            EXPECT((ny + n - 1) / n <= ly2 || ly2 >= ny);
+            if (n < ny) EXPECT(!(ny % n == 0 && (ny / n) % 16 == 0));
+        }
+    EXPECT(lbh::fused_nseg(4096, 92) == 45);
+    EXPECT(lbh::fused_nseg(1024, 140) == 9);    // 8 x 128 rows avoided
+    EXPECT(lbh::fused_nseg(384, 204) == 5);     // 3 x 128 and 4 x 96 avoided
+    EXPECT(lbh::fused_nseg(16, 16) == 2 && lbh::fused_nseg(16, 8) == 2);
+}
+
 int main()
 {
+    test_fused_segments();
     test_validate();
     test_cache();
     test_checkpoint();

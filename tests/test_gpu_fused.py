@@ -47,7 +47,7 @@ def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsio
                                                    (252, 31, True, True, 1), (8, 6, True, False, 64),
                                                    (1000, 40, False, False, 0), (6, 2, False, False, 0),
                                                    (122, 3, True, False, 2), (244, 17, True, True, 0),
-                                                   (10, 2, False, True, 0)])
+                                                   (10, 2, False, True, 0), (300, 53, True, True, 12)])
 def test_fused_bitwise_equals_single_steps(storage, nx, ny, walls, body, ly2, lanes):
     (p1, s1, t1), (p2, s2, t2) = _pair(nx, ny, storage, walls, body, 30, ly2, 32, lanes=lanes)
     assert t1 == t2 == 30
