@@ -28,8 +28,9 @@ length and the record of the 5000-step workload length.  `cpu_baseline` is
 the FP64 oracle on all host threads, with a single-thread rate beside it.
 
 Before each variant's warm-up, the same step kernel runs for half a second on
-a separate lattice of the same size and storage (clock ramp): the first tens
-of launches after a second of idle GPU run 3-15 % slow.
+a separate lattice of the same size and storage (clock ramp), the warm-up
+steps queued right behind it: the first tens of launches after even a few
+tens of milliseconds of idle GPU run 10-20 % slow.
 
 The launch shape comes from the project's autotuner (timed before the timed
 region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
@@ -120,29 +121,48 @@ def stated_precision(workload):
         return None
 
 
-def clock_ramp(variant, n, seconds, tune_cache=None, u=0.02):
-    """Runs the variant's step kernel for `seconds` on a separate n x n lattice
-    (uniform densities: cheap to set up; same kernel, launch shape and bytes
-    per step) and discards it.  Returns the steps taken."""
+def ramp_lattice(variant, n, tune_cache=None, u=0.02):
+    """A separate n x n lattice for the clock ramp (uniform densities: cheap to
+    set up; same kernel, launch shape and bytes per step as the variant)."""
     import numpy as np
-    import torch
     from paper_1004_5058_amd import inputs, lb
     vd = VARIANTS[variant]
     ra = np.full((n, n), 0.55)
     lat = lb.Lattice(n, n, ra, ra, None, None, u_top=u, u_bot=-u, storage=vd["storage"], profile=False,
                      **inputs.COUPLINGS)
+    if tune_cache is not None:
+        lat.autotune(tune_cache, steps=10)
+    if lat.launch()["steps_per_pass"] != vd["per_pass"]:
+        lat.set_fusion(vd["per_pass"])
+    return lat
+
+
+def run_ramp(lat, seconds, then=None):
+    """Steps the ramp lattice for `seconds`; `then` (the next work) is queued
+    right behind its last steps, so the GPU does not idle in between (even a
+    few tens of milliseconds idle let the clocks fall: the next 20-40
+    launches then run 10-20 % slow).  Returns the ramp steps taken."""
+    import torch
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        lat.step(64)
+        done += 64
+        if time.perf_counter() - t0 >= seconds:
+            break
+        torch.cuda.synchronize()
+    if then is not None:
+        then()
+    torch.cuda.synchronize()
+    return done
+
+
+def clock_ramp(variant, n, seconds, tune_cache=None, u=0.02):
+    """Runs the variant's step kernel for `seconds` on a separate lattice and
+    discards it (for work that follows at once).  Returns the steps taken."""
+    lat = ramp_lattice(variant, n, tune_cache=tune_cache, u=u)
     try:
-        if tune_cache is not None:
-            lat.autotune(tune_cache, steps=10)
-        if lat.launch()["steps_per_pass"] != vd["per_pass"]:
-            lat.set_fusion(vd["per_pass"])
-        done = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
-            lat.step(64)
-            torch.cuda.synchronize()
-            done += 64
-        return done
+        return run_ramp(lat, seconds)
     finally:
         lat.close()
         del lat
@@ -166,15 +186,27 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None, ramp_s=0
     shape = lat.launch()
     if vd["per_pass"] == 2:
         shape["lanes"], shape["columns"] = lat.fusion_tile()
-    ramp_steps = clock_ramp(variant, n, ramp_s, tune_cache=tune_cache) if ramp_s > 0 else 0
-    lat.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    # the timed region: `steps` steps bracketed by HIP events on the lattice's
-    # own stream (lb_time_steps), which give the device time per step
-    ms_kernel = lat.time_steps(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # clock ramp on a separate lattice, the warm-up steps queued right behind
+    # it; the ramp lattice is freed only after the timed region (freeing
+    # synchronises the device)
+    ramp = ramp_lattice(variant, n, tune_cache=tune_cache, u=u) if ramp_s > 0 else None
+    try:
+        if ramp is not None:
+            ramp_steps = run_ramp(ramp, ramp_s, then=lambda: lat.step(warmup))
+        else:
+            ramp_steps = 0
+            lat.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # the timed region: `steps` steps bracketed by HIP events on the
+        # lattice's own stream (lb_time_steps), which give the device time per step
+        ms_kernel = lat.time_steps(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        if ramp is not None:
+            ramp.close()
+            del ramp
     sb, st, ns = lat.stress()
     fields = lat.fields()
     lat.close()
@@ -482,7 +514,8 @@ def main():
                      "effective_gbs": round(vd["bytes_per_lup"] * lups / (r["ms_kernel"] * 1e-3) / 1e9, 1)},
         "variants": {},
         "clock_ramp": (f"{a.ramp:g} s of the same step kernel on a separate {n}x{n} lattice of the same storage "
-                       f"before the {a.warmup} warm-up steps ({r['ramp_steps']} steps)") if a.ramp > 0 else None,
+                       f"({r['ramp_steps']} steps), the {a.warmup} warm-up steps queued right behind it") if a.ramp > 0
+        else None,
     }
     for v in variants:
         d = VARIANTS[v]
