@@ -95,9 +95,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, variant):
-    """HBM bytes per kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def measured_counters(workload, variant):
+    """The committed rocprofv3 counter summary of a variant's step kernel
+    (HBM bytes per launch, VALU busy share), if it was taken on the current
+    kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -108,7 +109,14 @@ def measured_traffic(workload, variant):
     e = d.get(f"{workload}/{variant}")
     if not e or e.get("kernel_hash") != kernel_source_hash():
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def measured_traffic(workload, variant):
+    """HBM bytes per kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    e = measured_counters(workload, variant)
+    return None if e is None else e.get("bytes_per_launch")
 
 
 def stated_precision(workload):
@@ -511,7 +519,8 @@ def main():
                      "traffic": traffic,
                      "bytes_per_launch": bytes_launch, "steps_per_launch": vd["per_pass"],
                      "ms_per_launch": round(ms_launch, 5),
-                     "effective_gbs": round(vd["bytes_per_lup"] * lups / (r["ms_kernel"] * 1e-3) / 1e9, 1)},
+                     "effective_gbs": round(vd["bytes_per_lup"] * lups / (r["ms_kernel"] * 1e-3) / 1e9, 1),
+                     "valu_busy": (measured_counters(workload, head) or {}).get("valu_busy")},
         "variants": {},
         "clock_ramp": (f"{a.ramp:g} s of the same step kernel on a separate {n}x{n} lattice of the same storage "
                        f"({r['ramp_steps']} steps), the {a.warmup} warm-up steps queued right behind it") if a.ramp > 0
@@ -528,6 +537,13 @@ def main():
             "bytes_per_lup_one_step": d["bytes_per_lup"],
             "effective_gbs": round(d["bytes_per_lup"] * lups / (rv["ms_kernel"] * 1e-3) / 1e9, 1),
             "sigma_bot_top": [float(f"{x:.7e}") for x in rv["stress"]]}
+        mc = measured_counters(workload, v)
+        if mc is not None:
+            # counters of the committed profile on this kernel source: HBM bytes
+            # per launch over this run's launch time, and the VALU busy share
+            line["variants"][v]["measured_gbs"] = round(
+                mc["bytes_per_launch"] / (rv["ms_kernel"] * d["per_pass"] * 1e-3) / 1e9, 1)
+            line["variants"][v]["valu_busy"] = mc.get("valu_busy")
         if ref is not None:
             line["variants"][v]["err_vs_f64"] = dict(errors_vs_f64(rv, ref), steps=a.steps + a.warmup)
     stated = stated_precision(workload)

@@ -180,12 +180,15 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
  * runs alone.  Populations and wall stress are bitwise those of single
  * steps; the line profile (lb_profile), when on, is accumulated too, from
  * partial sums grouped by the fused kernel's tiles, so it agrees with single
- * steps to FP64 rounding.  Tiles of W columns x ly2 rows, W from
- * lb_set_fusion_tile (ly2 = 0: the height whose tiles, handed out greedily to
- * the blocks the device runs at once at h + 8 ticks per tile of h rows,
- * finish first).  LB_EINVAL unless the storage is LB_F32, LB_F16DEV or
- * LB_BF16DEV (the 16-bit forms: nx even) and the device grants the kernel's
- * shared memory. */
+ * steps to FP64 rounding.  Tiles of W columns (W from lb_set_fusion_tile)
+ * and at most ly2 rows: each lattice's rows are cut into ceil(ny / ly2)
+ * segments of near-equal height, one more while they would all be the same
+ * multiple of 16 rows; a batch hands out its lattices' tiles tallest segments
+ * first.  ly2 = 0: the height whose tiles, handed out greedily to the blocks
+ * the device runs at once at h + 8 ticks per tile of h rows, finish first.
+ * Results are bitwise independent of the tiles.  LB_EINVAL unless the storage
+ * is LB_F32, LB_F16DEV or LB_BF16DEV (the 16-bit forms: nx even) and the
+ * device grants the kernel's shared memory. */
 lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
 
 /* Block width of the two-steps-per-pass kernel: lanes = 128, 192 or 256
@@ -213,16 +216,16 @@ lb_status lb_get_launch(lb_handle* h, int32_t* bx, int32_t* ly, int32_t* steps_p
 lb_status lb_save(lb_handle* h, void* buf, size_t* bytes);
 lb_status lb_load(lb_handle* h, const void* buf, size_t bytes);
 
-/* Autotuner: times `steps` steps of every candidate launch shape (bx in
- * {64, 128, 256, 512} as lb_set_launch admits them, ly in {8..256}, shapes
- * within the device's shared memory per block; for batches also persistent grids of 1, 2
- * and 4 blocks per compute unit) on this lattice; where lb_set_fusion admits
- * two steps per pass (FP32, 16-bit), also that mode behind the best shape,
- * for each block width of lb_set_fusion_tile the device grants, at the
- * automatic tile height and at heights of 20 to 300 rows (odd multiples of
- * 4: power-of-two segment heights measured up to 40 % slower).  Applies the
- * fastest
- * (shape, steps per pass and fused width; *ms is its time per step) and
+/* Autotuner: after about 0.3 s of steps to bring the GPU's clocks up, times
+ * `steps` steps of every candidate launch shape (bx in {64, 128, 256, 512} as
+ * lb_set_launch admits them, ly in {8..256}, shapes within the device's shared
+ * memory per block; for batches also persistent grids of 1, 2 and 4 blocks
+ * per compute unit) on this lattice; where lb_set_fusion admits two steps per
+ * pass (FP32, 16-bit), also that mode behind the best shape, for each block
+ * width of lb_set_fusion_tile the device grants, at the automatic tile height
+ * and at heights of 20 to 300 rows (odd multiples of 4); then times the four
+ * fastest candidates twice more over 4 x steps steps.  Applies the fastest of
+ * those (shape, steps per pass and fused width; *ms is its time per step) and
  * restores the simulation state exactly (populations, accumulators, step
  * count).  cache_path (may be NULL): JSON file of {key: {bx, ly, grid,
  * fusion, ly2, fw, ms}}, key "<gfx arch>/<storage>/<nx>x<ny>" (batches:

@@ -23,7 +23,7 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    entry = {"bytes_per_launch": 123, "kernel_hash": bench.kernel_source_hash()}
+    entry = {"bytes_per_launch": 123, "valu_busy": 0.5, "kernel_hash": bench.kernel_source_hash()}
     (prof / "traffic.json").write_text(json.dumps({"w/f32x2": entry, "w/f16x2": dict(entry, kernel_hash="0" * 16)}))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # the hash is of the real sources; only the summary's location moves
@@ -31,6 +31,8 @@ def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("w", "f32x2") == 123
     assert bench.measured_traffic("w", "f16x2") is None       # taken on another kernel source
     assert bench.measured_traffic("w", "bf16x2") is None      # never measured
+    assert bench.measured_counters("w", "f32x2")["valu_busy"] == 0.5
+    assert bench.measured_counters("w", "f16x2") is None
 
 
 def test_committed_counters_match_the_committed_kernels():
