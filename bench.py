@@ -37,12 +37,14 @@ region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
 flow-curve points per hour on the batched 48-lattice ensemble (10 000 steps
 each) against a plain one-lattice-at-a-time loop; a third leg counts
 stress-controlled flow-curve points per hour with and without the surrogate.
+With --surrogate-check-size the stress-controlled leg runs again on the knee
+refinement's checking lattices (1024 x 512, 10 000 steps).
 With --knee, a network trained on 2000 ensemble lattices proposes flow-curve
 refinements near the yield stress, each checked by a 1024x512 lattice run.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--variants f32x2,f32,f16x2,bf16x2,f16dev,bf16dev,mom32] [--size 4096] [--no-flowcurve]
-       [--no-tune] [--no-surrogate] [--no-errors] [--ramp SECONDS] [--knee]
+       [--no-tune] [--no-surrogate] [--no-errors] [--ramp SECONDS] [--surrogate-check-size] [--knee]
 """
 import argparse
 import hashlib
@@ -319,7 +321,7 @@ def flowcurve_rates(steps, n_lat=48, seed=100, tune_cache=None):
                 speedup=round(wall_p / wall_b, 3), max_sigma_mismatch=agree, launch_shape=shape)
 
 
-def surrogate_rates(n_cases=10, k=4, storage="f32", plain=True):
+def surrogate_rates(n_cases=10, k=4, storage="f32", plain=True, size=None):
     """Stress-controlled flow-curve points per hour: the shear rate at which a
     fixed-coupling lattice reaches a target wall stress, accepted when a
     lattice run is within 1 % (every accepted point is a lattice result).  A
@@ -328,33 +330,47 @@ def surrogate_rates(n_cases=10, k=4, storage="f32", plain=True):
     with the surrogate, whose network the HIP kernels train on batch A's
     lattice runs (no separate ensemble; the training is charged) and which
     places batch B's runs.  The plain per-run loop (bisection, one lattice run
-    at a time) serves batch B for reference."""
+    at a time) serves batch B for reference.  size: None for the 256 x 128,
+    20 000-step task; "check" for the knee refinement's checking lattices
+    (1024 x 512, 10 000 steps, wall speeds 0.005-0.06, the cases' rates 4e-5
+    to 1.6e-4) with batch A's search shared by both streams and no plain loop."""
     from paper_1004_5058_amd import surrogate
     G = surrogate.GAIN
-    nx, ny, steps, seed = G["nx"], G["ny"], G["steps"], G["seed"]
-    S_lo, S_hi = 2 * G["u"][0] / ny, 2 * G["u"][1] / ny
+    if size == "check":
+        nx, ny, steps, seed, u = 1024, 512, 10000, G["seed"], (0.005, 0.06)
+        s_cases = (4e-5, 1.6e-4)
+        plain = False
+    else:
+        nx, ny, steps, seed, u = G["nx"], G["ny"], G["steps"], G["seed"], G["u"]
+        s_cases = (1.5e-4, 6e-4)
+    S_lo, S_hi = 2 * u[0] / ny, 2 * u[1] / ny
 
     def lattice(batched):
         return lambda pts: surrogate.lattice_stresses(pts, nx, ny, steps, seed, storage=storage, batched=batched)
-    cases_a = surrogate.draw_points(n_cases, 31, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
-    cases_b = surrogate.draw_points(n_cases, 47, (1.5e-4, 6e-4), (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
+    cases_a = surrogate.draw_points(n_cases, 31, s_cases, (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
+    cases_b = surrogate.draw_points(n_cases, 47, s_cases, (-9.2, -9.05), (7.9, 8.05), max_sum=-0.98)
     targets = lattice(True)(cases_a + cases_b)
     ta, tb = targets[:n_cases], targets[n_cases:]
-    out = dict(lattice=f"{nx}x{ny}", storage=storage, steps=steps, cases_per_batch=n_cases, runs_per_round=k)
-    r, _, sb_k = surrogate.stream_points(cases_a, ta, cases_b, tb, lattice(True), S_lo, S_hi, k=k)
+    out = dict(lattice=f"{nx}x{ny}", storage=storage, steps=steps, cases_per_batch=n_cases, runs_per_round=k,
+               rate_range=[S_lo, S_hi])
+    r, sa_k, sb_k = surrogate.stream_points(cases_a, ta, cases_b, tb, lattice(True), S_lo, S_hi, k=k)
     out["batched"] = r
-    print(f"# stress-controlled points ({storage}), batched k-section: {r}", file=sys.stderr, flush=True)
+    print(f"# stress-controlled points ({storage}, {nx}x{ny}), batched k-section: {r}", file=sys.stderr, flush=True)
     surr = surrogate.FlowSurrogate(max_rows=2048, seed=0)
+    reuse = (sa_k, r["A"]["rounds"], r["A"]["wall_s"]) if size == "check" else None
     r, _, sb_n = surrogate.stream_points(cases_a, ta, cases_b, tb, lattice(True), S_lo, S_hi, k=k,
-                                         use_network=True, surr=surr)
+                                         use_network=True, surr=surr, batch_a=reuse)
     # the network's error on batch B's lattice runs (after the fact)
     import numpy as np
     err = [abs(float(surr.predict(g1, g2, np.exp(x))[0]) - sig) / abs(sig)
            for s, (g1, g2, _) in zip(sb_n, cases_b) for x, _, sig in s.points]
     r["network_rel_err_on_B_runs"] = dict(median=float(f"{np.median(err):.3e}"),
                                           p90=float(f"{np.quantile(err, 0.9):.3e}"))
+    if reuse is not None:
+        r["A_reused"] = "batch A's k-section search and time shared with the k-section stream"
     out["batched_surrogate"] = r
-    print(f"# stress-controlled points ({storage}), batched with the surrogate: {r}", file=sys.stderr, flush=True)
+    print(f"# stress-controlled points ({storage}, {nx}x{ny}), batched with the surrogate: {r}", file=sys.stderr,
+          flush=True)
     if plain:
         t0 = time.perf_counter()
         ss = [surrogate.RootSearch(t, S_lo, S_hi, k=1) for t in tb]
@@ -447,6 +463,8 @@ def main():
     ap.add_argument("--flow-steps", type=int, default=10000)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the stress-controlled surrogate leg")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
+    ap.add_argument("--surrogate-check-size", action="store_true",
+                    help="add the surrogate leg at the knee refinement's checking size (1024x512, 10 000 steps)")
     ap.add_argument("--knee", action="store_true",
                     help="add the knee-refinement leg: a network trained on 2000 ensemble lattices proposes "
                          "refinements near the yield stress, each checked by a 1024x512 lattice run (minutes)")
@@ -570,6 +588,11 @@ def main():
             line["surrogate"] = surrogate_rates()
         except Exception as e:  # reported, never hidden
             line["surrogate"] = {"error": repr(e)}
+    if a.surrogate_check_size:
+        try:
+            line["surrogate_check_size"] = surrogate_rates(size="check")
+        except Exception as e:  # reported, never hidden
+            line["surrogate_check_size"] = {"error": repr(e)}
     if a.knee:
         from paper_1004_5058_amd import surrogate
         try:

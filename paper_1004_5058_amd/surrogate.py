@@ -495,14 +495,19 @@ def rows_of(searches, cases):
 
 
 def stream_points(cases_a, targets_a, cases_b, targets_b, lattice, S_lo, S_hi, k=4, use_network=False,
-                  surr=None, iters=4000, lr=3e-3, h0=0.1, log=None):
+                  surr=None, iters=4000, lr=3e-3, h0=0.1, log=None, batch_a=None):
     """Stress-controlled points for a stream of two batches of cases, batched:
     batch A by k-section; batch B by k-section, or, with use_network, by
     network placement, the network (surr, a FlowSurrogate) trained by the HIP
     kernels on every lattice run of batch A (the runs the stream has made
     anyway; no separate training ensemble).  lattice(list of (g1, g2, S)) ->
     list of sigma.  Returns a report with wall times (training included),
-    lattice runs, rounds and accepted points per batch."""
+    lattice runs, rounds and accepted points per batch.  batch_a: the
+    (solvers, rounds, wall seconds) of an earlier run of batch A with the
+    same arguments (the returned solvers and the report's A rounds and wall
+    time), reused instead of searching batch A again: its lattice runs are
+    deterministic, and reusing them charges the stream batch A's time as
+    measured then."""
     import time as _t
 
     def run(cases, targets, placement, model_of=None):
@@ -515,7 +520,7 @@ def stream_points(cases_a, targets_a, cases_b, targets_b, lattice, S_lo, S_hi, k
         return ss, rounds, _t.perf_counter() - t0
 
     out = {}
-    sa, ra, wa = run(cases_a, targets_a, "ksect")
+    sa, ra, wa = batch_a if batch_a is not None else run(cases_a, targets_a, "ksect")
     out["A"] = _summary(sa, ra, wa)
     t_train = 0.0
     if use_network:
