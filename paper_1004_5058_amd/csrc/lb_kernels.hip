@@ -538,13 +538,18 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             if constexpr (DMA32 || DMA16) {
                 if (dma_halo && wave == halo_wave(r) && lane < ndma) {
                     const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+                    // the slot's LDS base, opaque to the compiler (one scalar
+                    // add per load instead of hoisted, spilled destinations)
+                    __attribute__((address_space(3))) char* hb =
+                        (__attribute__((address_space(3))) char*)&hst[r & 3][0][0];
+                    asm volatile("" : "+s"(hb));
 #pragma unroll
                     for (int q = 0; q < 18; ++q) {
                         const int cx = CX[q % 9];
                         const unsigned vo = ro + ((DMA32 && cx > 0) ? vhl : ((DMA32 && cx < 0) ? vhr : vh));
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[r & 3][q][0], 4, vo,
-                            __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
+                            q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)(hb + q * sizeof(hst[0][0])),
+                            4, vo, __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
                     }
                 }
             }
@@ -928,12 +933,17 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             if (wave == halo_wave(r) && lane < ndma) {
                 const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
                 const int hs = hslot(r);
+                // the slot's LDS base, opaque to the compiler: the destination
+                // of each plane is then one scalar add per load instead of a
+                // value hoisted out of the tick loop (and spilled)
+                __attribute__((address_space(3))) char* hb = (__attribute__((address_space(3))) char*)&hst[hs][0][0];
+                asm volatile("" : "+s"(hb));
 #pragma unroll
                 for (int q = 0; q < 18; ++q) {
                     const int cx = CX[q % 9];
                     const unsigned vo = ro + ((!DMA16 && cx > 0) ? vhl : ((!DMA16 && cx < 0) ? vhr : vh));
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)&hst[hs][q][0], 4, vo,
+                        q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)(hb + q * sizeof(hst[0][0])), 4, vo,
                         __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
                 }
             }
