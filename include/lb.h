@@ -290,8 +290,9 @@ lb_status lbb_destroy(lbb_handle* h);
 
 /* Device time of the last `nsteps` steps of one lattice or batch, measured
  * with HIP events around the step kernels on the handle's stream: average
- * milliseconds per step-kernel launch.  Enqueues nsteps steps and
- * synchronises.  Used by the benchmark for the roofline figure. */
+ * milliseconds per time step (a two-steps-per-pass launch counts as two
+ * steps).  Enqueues nsteps steps and synchronises.  Used by the benchmark for
+ * the roofline figure. */
 lb_status lb_time_steps(lb_handle* h, int32_t nsteps, double* ms_per_step);
 lb_status lbb_time_steps(lbb_handle* h, int32_t nsteps, double* ms_per_step);
 /* lb_set_fusion, lb_set_fusion_tile and lb_get_fusion_tile for a batch. */
