@@ -106,17 +106,117 @@ __device__ __forceinline__ void st(rsrc_t r, unsigned voff, unsigned soff, typen
 {
     bstore<typename P::S>((typename P::S)v, r, voff, (unsigned)__builtin_amdgcn_readfirstlane((int)soff));
 }
+template <class P>
+__device__ __forceinline__ void st_s(rsrc_t r, unsigned voff, unsigned soff, typename P::S v)
+{
+    bstore<typename P::S>(v, r, voff, (unsigned)__builtin_amdgcn_readfirstlane((int)soff));
+}
+
+// A value of the arithmetic type, rounded to the storage format on its own:
+// the value is first rounded to the arithmetic type, so the compiler cannot
+// fuse the conversion into the multiply-add that produced it (for FP16 that
+// fusion, v_fma_mixlo_f16, rounds once and can differ in the last bit; which
+// stores it fuses would otherwise depend on the code around them).
+template <class S, class C>
+__device__ __forceinline__ S to_store(C x)
+{
+    if constexpr (std::is_same<S, C>::value) {
+        return x;
+    } else {
+        asm("" : "+v"(x));
+        return (S)x;
+    }
+}
 
 // The 18 populations of one site held in registers between the row load and
 // the collision: the arithmetic type for 32/64-bit storage; for 16-bit storage
 // the raw values, two per VGPR (d16 loads fill the low and high halves), and
-// converted when read.
+// converted when read.  Besides single values a row gives the sums the
+// collision needs, in one fixed order (left to right): the species densities
+// (dens), the momentum (mom), the deviation f_q - x of one population from a
+// value (dev), and the post-collision value f_q - w t in the storage format,
+// rounded once (post).
 template <class P, bool PACK = (sizeof(typename P::S) == 2)> struct Row;
+
+// The sums in the arithmetic type, through the row's operator[].
+template <class R, class C>
+__device__ __forceinline__ void row_dens(const R& f, C& da, C& db)
+{
+    da = f[0];
+    db = f[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) { da += f[q]; db += f[9 + q]; }
+}
+template <class R, class C>
+__device__ __forceinline__ void row_mom(const R& f, C& jx, C& jy)
+{
+    jx = (f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + (f[10] - f[12] + f[14] - f[15] - f[16] + f[17]);
+    jy = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
+}
+
+// FP16 halves enter FP32 sums through the mixed-precision multiply-add
+// v_fma_mix_f32 (an operand may be the low or high FP16 half of a VGPR): the
+// widening is exact and a*1 + c rounds once, so each step equals the FP32 add
+// of the converted value bit for bit, without the conversion instruction.
+// mix_acc: x + s h, mix_pair: a + s b, mix_dev: h - x (s = +1 or -1; h, a, b
+// the halves H, HA, HB of the packed pairs).
+template <int H, bool NEG>
+__device__ __forceinline__ float mix_acc(unsigned p, float x)
+{
+    float r;
+    if constexpr (NEG && H)
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(p), "v"(x));
+    else if constexpr (NEG)
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(p), "v"(x));
+    else if constexpr (H)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(p), "v"(x));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(p), "v"(x));
+    return r;
+}
+template <int HA, int HB, bool NEG>
+__device__ __forceinline__ float mix_pair(unsigned a, unsigned b)
+{
+    float r;
+    if constexpr (NEG)
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[%c3,0,%c4] op_sel_hi:[1,0,1]"
+            : "=v"(r) : "v"(b), "v"(a), "n"(HB), "n"(HA));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[%c3,0,%c4] op_sel_hi:[1,0,1]"
+            : "=v"(r) : "v"(b), "v"(a), "n"(HB), "n"(HA));
+    return r;
+}
+// The FP16 rounding of h - w t, rounded once (v_fma_mixlo_f16 writes the low
+// half of its destination).
+template <int H>
+__device__ __forceinline__ _Float16 mix_post(unsigned p, float w, float t)
+{
+    unsigned r;
+    if constexpr (H)
+        asm("v_fma_mixlo_f16 %0, -%1, %2, %3 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(w), "v"(t), "v"(p));
+    else
+        asm("v_fma_mixlo_f16 %0, -%1, %2, %3 op_sel:[0,0,0] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(w), "v"(t), "v"(p));
+    return __builtin_bit_cast(_Float16, (unsigned short)r);
+}
+template <int H>
+__device__ __forceinline__ float mix_dev(unsigned p, float x)
+{
+    float r;
+    if constexpr (H)
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(p), "v"(x));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(p), "v"(x));
+    return r;
+}
 
 template <class P> struct Row<P, false> {
     using C = typename P::C;
     C v[18];
     __device__ __forceinline__ C operator[](int q) const { return v[q]; }
+    __device__ __forceinline__ void dens(C& da, C& db) const { row_dens(*this, da, db); }
+    __device__ __forceinline__ void mom(C& jx, C& jy) const { row_mom(*this, jx, jy); }
+    __device__ __forceinline__ C dev(int q, C x) const { return v[q] - x; }
+    __device__ __forceinline__ C post(int q, C w, C t) const { return v[q] - w * t; }
     // Planes are stored shifted in x by c_ix: population q of the lane's node
     // sits one column left (c_ix = +1: vl), in place (vc) or one column right
     // (c_ix = -1: vr).  so: uniform SGPR byte offset; v*: per-lane byte offsets.
@@ -135,9 +235,61 @@ template <class P> struct Row<P, true> {
     using S = typename P::S;
     typedef S S2 __attribute__((ext_vector_type(2)));
     S2 v[9];
+    static constexpr bool MIX = std::is_same<S, _Float16>::value;
     __device__ __forceinline__ float operator[](int q) const
     {
         return (float)((q & 1) ? v[q >> 1].y : v[q >> 1].x);
+    }
+    template <int Q> __device__ __forceinline__ unsigned u() const { return __builtin_bit_cast(unsigned, v[Q >> 1]); }
+    template <int Q, bool NEG> __device__ __forceinline__ float acc(float x) const
+    {
+        return mix_acc<Q & 1, NEG>(u<Q>(), x);
+    }
+    template <int QA, int QB, bool NEG> __device__ __forceinline__ float pair() const
+    {
+        return mix_pair<QA & 1, QB & 1, NEG>(u<QA>(), u<QB>());
+    }
+    __device__ __forceinline__ void dens(float& da, float& db) const
+    {
+        if constexpr (MIX) {
+            da = acc<8, false>(acc<7, false>(acc<6, false>(acc<5, false>(
+                acc<4, false>(acc<3, false>(acc<2, false>(pair<0, 1, false>())))))));
+            db = acc<17, false>(acc<16, false>(acc<15, false>(acc<14, false>(
+                acc<13, false>(acc<12, false>(acc<11, false>(pair<9, 10, false>())))))));
+        } else {
+            row_dens(*this, da, db);
+        }
+    }
+    __device__ __forceinline__ void mom(float& jx, float& jy) const
+    {
+        if constexpr (MIX) {
+            const float ax = acc<8, false>(acc<7, true>(acc<6, true>(acc<5, false>(pair<1, 3, true>()))));
+            const float bx = acc<17, false>(acc<16, true>(acc<15, true>(acc<14, false>(pair<10, 12, true>()))));
+            const float ay = acc<8, true>(acc<7, true>(acc<6, false>(acc<5, false>(pair<2, 4, true>()))));
+            const float by = acc<17, true>(acc<16, true>(acc<15, false>(acc<14, false>(pair<11, 13, true>()))));
+            jx = ax + bx;
+            jy = ay + by;
+        } else {
+            row_mom(*this, jx, jy);
+        }
+    }
+    __device__ __forceinline__ float dev(int q, float x) const
+    {
+        if constexpr (MIX) {
+            const unsigned p = __builtin_bit_cast(unsigned, v[q >> 1]);
+            return (q & 1) ? mix_dev<1>(p, x) : mix_dev<0>(p, x);
+        } else {
+            return (*this)[q] - x;
+        }
+    }
+    __device__ __forceinline__ S post(int q, float w, float t) const
+    {
+        if constexpr (MIX) {
+            const unsigned p = __builtin_bit_cast(unsigned, v[q >> 1]);
+            return (q & 1) ? mix_post<1>(p, w, t) : mix_post<0>(p, w, t);
+        } else {
+            return (S)((*this)[q] - w * t);
+        }
     }
     __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, unsigned so,
                                          unsigned pbytes)
@@ -504,12 +656,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             fr.load(rin0, rin1, (unsigned)wrap(col - 1) * es + ro, (unsigned)col * es + ro,
                     (unsigned)wrap(col + 1) * es + ro, 0, pbytes);
         };
-        auto dens = [&](const R& fr, C& da, C& db) {
-            da = fr[0];
-            db = fr[9];
-#pragma unroll
-            for (int q = 1; q < 9; ++q) { da += fr[q]; db += fr[9 + q]; }
-        };
+        auto dens = [&](const R& fr, C& da, C& db) { fr.dens(da, db); };
 
         // Halo columns x0-2, x0-1, x0+BX, x0+BX+1 for every row of the segment
         // (formats without the direct-to-LDS halo).
@@ -631,10 +778,8 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
             const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
             const C FxB = -pb * sxB - rb * cxB, FyB = -pb * syB - rb * cyB;
 
-            const C jx = (f[1] - f[3] + f[5] - f[6] - f[7] + f[8])
-                       + (f[10] - f[12] + f[14] - f[15] - f[16] + f[17]);
-            const C jy = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8])
-                       + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
+            C jx, jy;
+            f.mom(jx, jy);
             const C inv_rho = rcp(ra + rb);
             const C ux = jx * inv_rho, uy = jy * inv_rho;
             // external body force of the row, shared by density: the same
@@ -667,19 +812,23 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                 const C r0 = rs * (C)(4.0 / 9.0), r1 = rs * (C)(1.0 / 9.0), r2 = rs * (C)(1.0 / 36.0);
                 const C d1 = drs * (C)(1.0 / 9.0), d2 = drs * (C)(1.0 / 36.0);
                 const int o = 9 * s;
-                C fs[9];
-                fs[0] = f[o + 0] - omega * (f[o + 0] - (drs * (C)(4.0 / 9.0) - r0 * usq));
+                // t_i = f_i - f^eq_i; the post-collision value f_i - omega t_i
+                // is stored rounded once to the storage format (post); the
+                // wall rows also use it in the arithmetic type (fs)
+                C t[9];
+                t[0] = f.dev(o + 0, drs * (C)(4.0 / 9.0) - r0 * usq);
                 auto pair = [&](int ip, int im, C rw, C dw, C cu) {
                     const C sym = dw + rw * ((C)4.5 * cu * cu - usq);
                     const C anti = rw * ((C)3 * cu);
-                    fs[ip] = f[o + ip] - omega * (f[o + ip] - (sym + anti));
-                    fs[im] = f[o + im] - omega * (f[o + im] - (sym - anti));
+                    t[ip] = f.dev(o + ip, sym + anti);
+                    t[im] = f.dev(o + im, sym - anti);
                 };
                 pair(1, 3, r1, d1, vx);
                 pair(2, 4, r1, d1, vy);
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
                 if (!valid) return;
+                auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
                 const rsrc_t ro = (s == 0) ? rout0 : rout1;
                 if (!(bot || top)) {
                     // interior row: push to rows y-1, y, y+1 (periodic wrap)
@@ -687,7 +836,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                     for (int i = 0; i < 9; ++i) {
                         const int cy = CY[i];
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
+                        st_s<P>(ro, vrow + vc, i * pbytes, f.post(o + i, omega, t[i]));
                     }
                     return;
                 }
@@ -697,17 +846,19 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                 for (int i = 0; i < 9; ++i) {
                     const int cx = CX[i], cy = CY[i];
                     const unsigned vback = (cx == 0) ? vc : (cx > 0 ? vp : vm);
-                    if (cy < 0 && bot) {
-                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
-                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
-                        if (cx != 0) mom_b += (C)cx * (fs[i] + back);
-                    } else if (cy > 0 && top) {
-                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
-                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
-                        if (cx != 0) mom_t += (C)cx * (fs[i] + back);
+                    if ((cy < 0 && bot) || (cy > 0 && top)) {
+                        const C uw = (cy < 0) ? u_bot : u_top;
+                        if (cx != 0) {
+                            const C back = fs(i) - (C)(1.0 / 6.0) * rs * (C)cx * uw;
+                            st_s<P>(ro, vrow_0 + vback, OPP[i] * pbytes, to_store<S>(back));
+                            if (cy < 0) mom_b += (C)cx * (fs(i) + back);
+                            else mom_t += (C)cx * (fs(i) + back);
+                        } else {
+                            st_s<P>(ro, vrow_0 + vback, OPP[i] * pbytes, f.post(o + i, omega, t[i]));
+                        }
                     } else {
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
+                        st_s<P>(ro, vrow + vc, i * pbytes, f.post(o + i, omega, t[i]));
                     }
                 }
             };
@@ -911,11 +1062,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             d.off_prof >= 0 ? (double*)(base + d.off_prof) + (long long)d.ngroups * ny : nullptr;
         C mom_b = 0, mom_t = 0;
         // populations returned into row ny - 1 at a top wall, held one tick,
-        // rounded to the storage format where they are computed (the
-        // conversion of the multiply-add's result then rounds as k_step's
-        // store of the same expression: for FP16 the compiler fuses the two
-        // into one multiply-add rounded once to FP16, which a later
-        // conversion of an FP32 value would not reproduce)
+        // already in the storage format (the values k_step stores)
         S held[2][3] = {{(S)0, (S)0, (S)0}, {(S)0, (S)0, (S)0}};
 
         using R = Row<P>;
@@ -923,12 +1070,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
             fr.load(rin0, rin1, vm + ro, vc + ro, vp + ro, 0, pbytes);
         };
-        auto dens = [&](const R& fr, C& da, C& db) {
-            da = fr[0];
-            db = fr[9];
-#pragma unroll
-            for (int q = 1; q < 9; ++q) { da += fr[q]; db += fr[9 + q]; }
-        };
+        auto dens = [&](const R& fr, C& da, C& db) { fr.dens(da, db); };
         auto halo_fetch = [&](int r) {
             if (wave == halo_wave(r) && lane < ndma) {
                 const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
@@ -1051,10 +1193,8 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             const C pa = pref0 + p0.x, pb = pref1 + p0.y;
             const C FxA = -pa * sxA - ra * cxA, FyA = -pa * syA - ra * cyA;
             const C FxB = -pb * sxB - rb * cxB, FyB = -pb * syB - rb * cyB;
-            const C jx = (f[1] - f[3] + f[5] - f[6] - f[7] + f[8])
-                       + (f[10] - f[12] + f[14] - f[15] - f[16] + f[17]);
-            const C jy = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8])
-                       + (f[11] - f[13] + f[14] + f[15] - f[16] - f[17]);
+            C jx, jy;
+            f.mom(jx, jy);
             const C inv_rho = rcp(ra + rb);
             const C ux = jx * inv_rho, uy = jy * inv_rho;
             C gx = (C)0;
@@ -1104,18 +1244,23 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 const C r0 = rs * (C)(4.0 / 9.0), r1 = rs * (C)(1.0 / 9.0), r2 = rs * (C)(1.0 / 36.0);
                 const C d1 = drs * (C)(1.0 / 9.0), d2 = drs * (C)(1.0 / 36.0);
                 const int o = 9 * s;
-                C fs[9];
-                fs[0] = f[o + 0] - omega * (f[o + 0] - (drs * (C)(4.0 / 9.0) - r0 * usq));
+                // t_i = f_i - f^eq_i; stored values as k_step's (post: rounded
+                // once to the storage format; fs: the arithmetic type, for the
+                // wall rows)
+                C t[9];
+                t[0] = f.dev(o + 0, drs * (C)(4.0 / 9.0) - r0 * usq);
                 auto pair = [&](int ip, int im, C rw, C dw, C cu) {
                     const C sym = dw + rw * ((C)4.5 * cu * cu - usq);
                     const C anti = rw * ((C)3 * cu);
-                    fs[ip] = f[o + ip] - omega * (f[o + ip] - (sym + anti));
-                    fs[im] = f[o + im] - omega * (f[o + im] - (sym - anti));
+                    t[ip] = f.dev(o + ip, sym + anti);
+                    t[im] = f.dev(o + im, sym - anti);
                 };
                 pair(1, 3, r1, d1, vx);
                 pair(2, 4, r1, d1, vy);
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
+                auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
+                auto post = [&](int i) -> S { return f.post(o + i, omega, t[i]); };
                 if (k == 0) {
                     // into the ring: row y + c_iy at the lane's own index; a
                     // population leaving through a wall returns as OPP[i] at
@@ -1123,17 +1268,25 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         const int cx = CX[i], cy = CY[i];
-                        if (cy < 0 && bot) {
-                            const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
-                            const int oi = OPP[i];
-                            pring[pr[pr_class(CY[oi])][1]][3 * s + pr_k(oi)][j + 1 + cx] = (S)back;
-                            if (cx != 0 && count) mom_b += (C)cx * (fs[i] + back);
-                        } else if (cy > 0 && top) {
-                            const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
-                            held[s][pr_k(OPP[i])] = (S)back;   // written at tick ny
-                            if (cx != 0 && count) mom_t += (C)cx * (fs[i] + back);
+                        if ((cy < 0 && bot) || (cy > 0 && top)) {
+                            const C uw = (cy < 0) ? u_bot : u_top;
+                            S sback = post(i);
+                            if (cx != 0) {
+                                const C back = fs(i) - (C)(1.0 / 6.0) * rs * (C)cx * uw;
+                                sback = to_store<S>(back);
+                                if (count) {
+                                    if (cy < 0) mom_b += (C)cx * (fs(i) + back);
+                                    else mom_t += (C)cx * (fs(i) + back);
+                                }
+                            }
+                            if (cy < 0) {
+                                const int oi = OPP[i];
+                                pring[pr[pr_class(CY[oi])][1]][3 * s + pr_k(oi)][j + 1 + cx] = sback;
+                            } else {
+                                held[s][pr_k(OPP[i])] = sback;   // written at tick ny
+                            }
                         } else {
-                            pring[pr[pr_class(cy)][cy + 1]][3 * s + pr_k(i)][j + 1] = (S)fs[i];
+                            pring[pr[pr_class(cy)][cy + 1]][3 * s + pr_k(i)][j + 1] = post(i);
                         }
                     }
                     return;
@@ -1145,7 +1298,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                     for (int i = 0; i < 9; ++i) {
                         const int cy = CY[i];
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
+                        st_s<P>(ro, vrow + vc, i * pbytes, post(i));
                     }
                     return;
                 }
@@ -1153,17 +1306,19 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 for (int i = 0; i < 9; ++i) {
                     const int cx = CX[i], cy = CY[i];
                     const unsigned vback = (cx == 0) ? vc : (cx > 0 ? vp : vm);
-                    if (cy < 0 && bot) {
-                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_bot : fs[i];
-                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
-                        if (cx != 0) mom_b += (C)cx * (fs[i] + back);
-                    } else if (cy > 0 && top) {
-                        const C back = (cx != 0) ? fs[i] - (C)(1.0 / 6.0) * rs * (C)cx * u_top : fs[i];
-                        st<P>(ro, vrow_0 + vback, OPP[i] * pbytes, back);
-                        if (cx != 0) mom_t += (C)cx * (fs[i] + back);
+                    if ((cy < 0 && bot) || (cy > 0 && top)) {
+                        const C uw = (cy < 0) ? u_bot : u_top;
+                        if (cx != 0) {
+                            const C back = fs(i) - (C)(1.0 / 6.0) * rs * (C)cx * uw;
+                            st_s<P>(ro, vrow_0 + vback, OPP[i] * pbytes, to_store<S>(back));
+                            if (cy < 0) mom_b += (C)cx * (fs(i) + back);
+                            else mom_t += (C)cx * (fs(i) + back);
+                        } else {
+                            st_s<P>(ro, vrow_0 + vback, OPP[i] * pbytes, post(i));
+                        }
                     } else {
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        st<P>(ro, vrow + vc, i * pbytes, fs[i]);
+                        st_s<P>(ro, vrow + vc, i * pbytes, post(i));
                     }
                 }
             };

@@ -2,8 +2,8 @@
 storage): the fused kernel keeps step t's populations in on-chip memory and
 runs step t+1 behind it.  It performs the operations of two single steps on the
 same values (the library is built with multiply-add contraction inside
-expressions only; the ring holds them rounded to the storage format, as HBM
-would), so populations, wall stresses and step counts must equal the
+expressions only; every stored value is rounded to the storage format by one
+rule that both kernels share, and the ring holds it as HBM would), so populations, wall stresses and step counts must equal the
 single-step path bit for bit, with walls or periodic y, body force, any tile
 height and block width (128, 192, 256 lanes per step), odd step counts (the
 last step runs alone) and graphs of either parity."""
@@ -21,11 +21,13 @@ def _gpu():
     need_gpu()
 
 
-def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsion", lanes=0):
+def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsion", lanes=0, tau=None):
     u = 0.02 if walls else 0.0
     ra, rb = (inputs.emulsion(nx, ny, seed=seed) if init == "emulsion" else inputs.noise(nx, ny, seed))
     ux, uy = inputs.couette(nx, ny, u, -u) if walls else (None, None)
     kw = dict(fx_amp=3e-5, fx_k=0.21) if body else {}
+    if tau is not None:
+        kw["tau"] = tau
     out = []
     for fused in (False, True):
         lat = gpu_lattice(nx, ny, ra, rb, ux, uy, walls=walls, u_top=u, u_bot=-u, storage=storage, **kw)
@@ -50,6 +52,22 @@ def _pair(nx, ny, storage, walls, body, steps, ly2, graph, seed=5, init="emulsio
                                                    (10, 2, False, True, 0), (300, 53, True, True, 12)])
 def test_fused_bitwise_equals_single_steps(storage, nx, ny, walls, body, ly2, lanes):
     (p1, s1, t1), (p2, s2, t2) = _pair(nx, ny, storage, walls, body, 30, ly2, 32, lanes=lanes)
+    assert t1 == t2 == 30
+    np.testing.assert_array_equal(p2, p1)
+    assert s2 == s1
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("tau", [0.83, 1.37])
+@pytest.mark.parametrize("walls,body", [(True, False), (False, True)])
+def test_fused_bitwise_any_tau(storage, tau, walls, body):
+    """Away from tau = 1 the relaxation f - omega (f - f^eq) is not f^eq, so
+    the rounding of the stored value matters: each stored value is defined
+    once (FP16: the post-collision multiply-add rounded once to FP16; values
+    bounced at a wall rounded to FP32 first) and both kernels store exactly
+    that, with walls (every wall path, both walls moving) or periodic y with
+    the body force."""
+    (p1, s1, t1), (p2, s2, t2) = _pair(300, 53, storage, walls, body, 30, 12, 32, tau=tau)
     assert t1 == t2 == 30
     np.testing.assert_array_equal(p2, p1)
     assert s2 == s1
