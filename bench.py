@@ -90,10 +90,16 @@ def variant_storage(v):
 
 
 def kernel_source_hash():
+    """Hash of the step kernels' source code, comments and layout removed (a
+    comment edit leaves the committed counters valid; a code change does not)."""
+    import re
     h = hashlib.sha256()
     for name in ("lb_kernels.hip", "lb_device.hpp"):
-        with open(os.path.join(ROOT, "paper_1004_5058_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1004_5058_amd", "csrc", name), encoding="utf-8") as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -131,14 +137,20 @@ def stated_precision(workload):
         return None
 
 
-def ramp_lattice(variant, n, tune_cache=None, u=0.02):
-    """A separate n x n lattice for the clock ramp (uniform densities: cheap to
-    set up; same kernel, launch shape and bytes per step as the variant)."""
+def ramp_lattice(variant, n, tune_cache=None, u=0.02, fields=None):
+    """A separate n x n lattice for the clock ramp: same kernel, launch shape
+    and bytes per step as the variant, and with `fields` (rho_a, rho_b, ux, uy)
+    the same initial state as the timed lattice (the clocks the GPU settles at
+    depend on the data it computes on: after a ramp on uniform densities the
+    16-bit forms ran their first timed launches up to 5 % slow); without,
+    uniform densities (cheap to set up)."""
     import numpy as np
     from paper_1004_5058_amd import inputs, lb
     vd = VARIANTS[variant]
-    ra = np.full((n, n), 0.55)
-    lat = lb.Lattice(n, n, ra, ra, None, None, u_top=u, u_bot=-u, storage=vd["storage"], profile=False,
+    if fields is None:
+        ra = np.full((n, n), 0.55)
+        fields = (ra, ra, None, None)
+    lat = lb.Lattice(n, n, *fields, u_top=u, u_bot=-u, storage=vd["storage"], profile=False,
                      **inputs.COUPLINGS)
     if tune_cache is not None:
         lat.autotune(tune_cache, steps=10)
@@ -186,7 +198,6 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None, ramp_s=0
     ux, uy = inputs.couette(n, n, u, -u)
     lat = lb.Lattice(n, n, ra, rb, ux, uy, u_top=u, u_bot=-u, storage=vd["storage"], profile=False,
                      **inputs.COUPLINGS)
-    del ra, rb, ux, uy
     if tune_cache is not None:
         lat.autotune(tune_cache, steps=10)
     # the tuner may pick either; each variant states its own steps per pass
@@ -196,10 +207,11 @@ def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None, ramp_s=0
     shape = lat.launch()
     if vd["per_pass"] == 2:
         shape["lanes"], shape["columns"] = lat.fusion_tile()
-    # clock ramp on a separate lattice, the warm-up steps queued right behind
-    # it; the ramp lattice is freed only after the timed region (freeing
-    # synchronises the device)
-    ramp = ramp_lattice(variant, n, tune_cache=tune_cache, u=u) if ramp_s > 0 else None
+    # clock ramp on a separate lattice from the same initial state, the
+    # warm-up steps queued right behind it; the ramp lattice is freed only
+    # after the timed region (freeing synchronises the device)
+    ramp = ramp_lattice(variant, n, tune_cache=tune_cache, u=u, fields=(ra, rb, ux, uy)) if ramp_s > 0 else None
+    del ra, rb, ux, uy
     try:
         if ramp is not None:
             ramp_steps = run_ramp(ramp, ramp_s, then=lambda: lat.step(warmup))

@@ -187,15 +187,17 @@ lb_status lb_set_graph(lb_handle* h, int32_t steps_per_graph);
  * first.  ly2 = 0: the height whose tiles, handed out greedily to the blocks
  * the device runs at once at h + 8 ticks per tile of h rows, finish first.
  * Results are bitwise independent of the tiles.  LB_EINVAL unless the storage
- * is LB_F32, LB_F16DEV or LB_BF16DEV (the 16-bit forms: nx even) and the
- * device grants the kernel's shared memory. */
+ * is LB_F32, LB_F16DEV or LB_BF16DEV and the device grants the kernel's
+ * shared memory. */
 lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
 
 /* Block width of the two-steps-per-pass kernel: lanes = 128, 192 or 256
  * threads per time step (the block has twice as many), or 0 for the width
  * with the most waves resident per compute unit.  A tile stores lanes - 6
- * columns (FP32) or lanes - 8 (16-bit): the step-t columns beyond them are the
- * overlap step t+1 needs.  Results are bitwise independent of the width.
+ * columns (FP32) or lanes - 10 (16-bit): the step-t columns beyond them are
+ * the overlap step t+1 needs (16-bit: also the two columns each side whose
+ * densities step t's stencil needs, where FP32 loads them as halo columns).
+ * Results are bitwise independent of the width.
  * LB_EINVAL for another value. */
 lb_status lb_set_fusion_tile(lb_handle* h, int32_t lanes);
 /* The width in effect (automatic choice resolved) and its stored columns per

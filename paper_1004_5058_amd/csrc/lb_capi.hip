@@ -840,15 +840,10 @@ lb_status set_launch(lbb_handle* h, int bx, int ly, int grid)
 }
 
 // Whether the handle may run two steps per pass: FP32 or 16-bit population
-// storage (the 16-bit forms take their halo columns in aligned pairs: every
-// lattice needs an even nx).
+// storage.
 bool fusion_allowed(const lbb_handle* h)
 {
-    if (!fusion_storage(h->storage)) return false;
-    if (h->storage != LB_F32)
-        for (const Lat& a : h->lats)
-            if (a.p.nx % 2) return false;
-    return true;
+    return fusion_storage(h->storage);
 }
 
 // The fused kernel's LDS for nw waves per step, checked against the device.
@@ -872,7 +867,7 @@ lb_status set_fusion(lbb_handle* h, int k, int ly2)
     if (ly2 < 0) return fail(LB_EINVAL, "ly2 must be >= 0");
     if (k == 2) {
         if (!fusion_allowed(h))
-            return fail(LB_EINVAL, "two steps per pass need FP32 or 16-bit population storage (16-bit: even nx)");
+            return fail(LB_EINVAL, "two steps per pass need FP32 or 16-bit population storage");
         const int nw = h->fnw > 0 ? h->fnw : auto_fnw(h);
         lb_status st = check_fused_lds(h, nw);
         if (st != LB_OK) return st;

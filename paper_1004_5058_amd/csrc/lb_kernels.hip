@@ -112,6 +112,15 @@ __device__ __forceinline__ void st_s(rsrc_t r, unsigned voff, unsigned soff, typ
     bstore<typename P::S>(v, r, voff, (unsigned)__builtin_amdgcn_readfirstlane((int)soff));
 }
 
+// A copy of x the compiler cannot see through: an expression written with it
+// is never merged with the same expression written with x.
+template <class T>
+__device__ __forceinline__ T opaque(T x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+
 // A value of the arithmetic type, rounded to the storage format on its own:
 // the value is first rounded to the arithmetic type, so the compiler cannot
 // fuse the conversion into the multiply-add that produced it (for FP16 that
@@ -282,6 +291,8 @@ template <class P> struct Row<P, true> {
             return (*this)[q] - x;
         }
     }
+    // FP16: one v_fma_mixlo_f16 written out (left to the compiler, whether the
+    // conversion fused into the multiply-add depended on the surrounding code)
     __device__ __forceinline__ S post(int q, float w, float t) const
     {
         if constexpr (MIX) {
@@ -596,6 +607,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const unsigned xm = (xc == 0) ? (unsigned)(nx - 1) : xc - 1;
 
         const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
+        const C omega_w = opaque(omega);   // the wall rows' omega (fs below)
         const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
         C ks0[5], ks1[5];
 #pragma unroll
@@ -828,7 +840,15 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
                 if (!valid) return;
-                auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
+                // the nine stored values, rounded once each (post), before any
+                // wall branch: computed together they schedule better than at
+                // each store (about 1 % of the FP16 two-step kernel); the wall
+                // rows also use the value in the arithmetic type (fs, with a
+                // copy of omega: its multiply-add stays apart from post's)
+                S ps[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) ps[i] = f.post(o + i, omega, t[i]);
+                auto fs = [&](int i) -> C { return f[o + i] - omega_w * t[i]; };
                 const rsrc_t ro = (s == 0) ? rout0 : rout1;
                 if (!(bot || top)) {
                     // interior row: push to rows y-1, y, y+1 (periodic wrap)
@@ -836,7 +856,7 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                     for (int i = 0; i < 9; ++i) {
                         const int cy = CY[i];
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        st_s<P>(ro, vrow + vc, i * pbytes, f.post(o + i, omega, t[i]));
+                        st_s<P>(ro, vrow + vc, i * pbytes, ps[i]);
                     }
                     return;
                 }
@@ -854,11 +874,11 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                             if (cy < 0) mom_b += (C)cx * (fs(i) + back);
                             else mom_t += (C)cx * (fs(i) + back);
                         } else {
-                            st_s<P>(ro, vrow_0 + vback, OPP[i] * pbytes, f.post(o + i, omega, t[i]));
+                            st_s<P>(ro, vrow_0 + vback, OPP[i] * pbytes, ps[i]);
                         }
                     } else {
                         const unsigned vrow = (cy < 0) ? vrow_m : (cy > 0 ? vrow_p : vrow_0);
-                        st_s<P>(ro, vrow + vc, i * pbytes, f.post(o + i, omega, t[i]));
+                        st_s<P>(ro, vrow + vc, i * pbytes, ps[i]);
                     }
                 }
             };
@@ -933,9 +953,14 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
 // so the pair of steps is bitwise that of two k_step launches; each
 // population crosses HBM once per two updates.
 //
-// Column offset XO: 4-byte storage 3 (TW = BW - 6).  2-byte storage 4
-// (TW = BW - 8): step t's tile then starts at an even column, so its halo
-// columns come in aligned column pairs, as in k_step (needs an even nx).
+// Column offset XO.  FP32: 3 (TW = BW - 6); step t's stencil reads the two
+// columns beyond each side of its lanes as halo columns (direct-to-LDS loads
+// by one wave per row, as in k_step).  16-bit: 5 (TW = BW - 10); the tile
+// overlaps its neighbours by two more columns each side instead, so every
+// wave does the same work per tick (no halo wave for the others to wait for
+// at the barrier): about 3 % (FP16) and 4 % (BF16) faster per step at 4096^2
+// than the halo form, which for FP32 with its narrower 128-lane tiles was 6 %
+// slower.  The edge lanes' results feed no output.
 //
 // The population ring is split by the y direction of the population, since
 // each class lives for a different number of ticks (rows r written at
@@ -949,7 +974,9 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
 // five-row rho ring (the rho stencil is belt 1 only) three blocks of 128
 // FP32 lanes per step fit in a CU's 160 KiB of LDS.
 template <class P> struct Fuse2Geom {
-    static constexpr int XO = sizeof(typename P::S) == 2 ? 4 : 3;
+    // FP32: halo columns by direct-to-LDS loads; 16-bit: overlapping tiles
+    static constexpr bool HALO = sizeof(typename P::S) == 4;
+    static constexpr int XO = HALO ? 3 : 5;
 };
 constexpr int pr_class(int cy) { return cy > 0 ? 0 : (cy == 0 ? 1 : 2); }
 // index of direction i within its class: (2, 5, 6), (0, 1, 3), (4, 7, 8)
@@ -966,10 +993,12 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     using C2 = typename V2<C>::T;
     static_assert(sizeof(S) <= 4, "two fused steps: 4- and 2-byte storage");
     constexpr bool DMA16 = sizeof(S) == 2;
+    constexpr bool HALO = Fuse2Geom<P>::HALO;
     constexpr int XO = Fuse2Geom<P>::XO;
     constexpr int TW = BW - 2 * XO;
-    using HT = std::conditional_t<DMA16, unsigned short, unsigned>;
-    // psi rings [step][slot][column index j + 2] (six rows), rho rings (five rows)
+    // psi rings [step][slot][column index j + 2] (six rows), rho rings (five
+    // rows); indices 0, 1, BW + 2 and BW + 3 are step t's halo columns (FP32)
+    // or stay zero (16-bit)
     __shared__ C2 ringP[2][6][BW + 4];
     __shared__ C2 ringR[2][5][BW + 4];
     // step t+1's input, after streaming: class rows 0..3 (c_y = +1, slot r & 3),
@@ -977,21 +1006,37 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     // class's three directions); index j + 1, one spare entry each side for the
     // values a wall returns to the neighbouring column
     __shared__ S pring[9][6][BW + 2];
-    // direct-to-LDS halo columns of step t: HS rows (a multiple of the number
-    // of halo waves, so rows sharing a slot share a wave)
-    constexpr int HS = (NW == 3) ? 6 : 4;
-    __shared__ HT hst[HS][18][DMA16 ? 12 : 4];
+    // FP32: step t's four halo columns by direct-to-LDS loads, four rows (a
+    // multiple of the number of halo waves, so rows sharing a slot share a wave)
+    constexpr int HS = HALO ? ((NW == 3) ? 6 : 4) : 1;
+    __shared__ unsigned hst[HS][18][HALO ? 4 : 1];
     __shared__ C momx[2][BW];          // step t's wall momentum, handed to step t+1
 
     const int tid = threadIdx.x;
     const int role = __builtin_amdgcn_readfirstlane(tid / BW);   // 0: step t, 1: step t+1
     const int j = tid - role * BW;
     const int wave = __builtin_amdgcn_readfirstlane(j >> 6), lane = tid & 63;
-    // step t's per-row halo work rotates over its waves
-    // (rows reach down to y0 - 5 >= -5; 24 is a multiple of NW and HS, so the
-    // unsigned remainders are those of r)
+    // FP32: step t's per-row halo work rotates over its waves (rows reach down
+    // to y0 - 5 >= -5; 24 is a multiple of NW and HS, so the unsigned
+    // remainders are those of r)
     auto halo_wave = [&](int r) { return (int)((unsigned)(r + 24) % (unsigned)NW); };
     auto hslot = [&](int r) { return (int)((unsigned)(r + 24) % (unsigned)HS); };
+    // 16-bit: step t's tile overlaps its neighbours by two more columns each
+    // side instead of loading halo columns, and the edge lanes read ring
+    // entries no lane writes (no output depends on them): zero, so that they
+    // compute finite values.  The first tick's barrier orders these stores
+    // before any read.
+    if constexpr (!HALO)
+    for (int e = tid; e < 22 * 4 + 54 * 2; e += 128 * NW) {
+        if (e < 88) {
+            const int r = e >> 2, c = e & 3, idx = c < 2 ? c : BW + c;
+            if (r < 12) ringP[r / 6][r % 6][idx] = C2{(C)0, (C)0};
+            else ringR[(r - 12) / 5][(r - 12) % 5][idx] = C2{(C)0, (C)0};
+        } else {
+            const int r = (e - 88) >> 1;
+            pring[r / 6][r % 6][(e & 1) ? BW + 1 : 0] = (S)0;
+        }
+    }
 
     for (int w = blockIdx.x; w < ntot; w += gridDim.x) {
         const int L = tiles[w];
@@ -1018,6 +1063,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const bool own = j >= XO && j < XO + TW && X + (j - XO) < nx;
 
         const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
+        const C omega_w = opaque(omega);   // the wall rows' omega (fs below)
         const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
         C ks0[5], ks1[5];
 #pragma unroll
@@ -1039,20 +1085,16 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const int es = (int)sizeof(S);
         const unsigned vc = xc * es, vp = xp * es, vm = xm * es;
         const unsigned pbytes = (unsigned)(plane * es), rbytes = (unsigned)(pitch * es);
-        // step t's halo columns by direct-to-LDS loads, as in k_step.  4-byte
-        // storage, lanes 0..3: columns x0-2, x0-1, x0+BW, x0+BW+1 and their
-        // left and right neighbours; 2-byte storage, lanes 0..5: the column
-        // pairs starting at x0-4, x0-2, x0, x0+BW-2, x0+BW, x0+BW+2.
+        // FP32 halo, lanes 0..3 of the row's halo wave: columns x0-2, x0-1,
+        // x0+BW, x0+BW+1 and their left and right neighbours (the planes are
+        // stored shifted by c_ix)
         unsigned vh = 0, vhl = 0, vhr = 0;
-        if (lane < 6) {
-            const int hc = DMA16 ? ((lane < 3) ? x0 - 4 + 2 * lane : x0 + BW - 8 + 2 * lane)
-                                 : ((lane < 2) ? x0 - 2 + lane : x0 + BW + lane - 2);
+        if (HALO && lane < 4) {
+            const int hc = (lane < 2) ? x0 - 2 + lane : x0 + BW + lane - 2;
             vh = (unsigned)wrap(hc) * es;
             vhl = (unsigned)wrap(hc - 1) * es;
             vhr = (unsigned)wrap(hc + 1) * es;
         }
-        const int ndma = DMA16 ? 6 : 4;
-        const int hb16 = (lane < 2) ? 2 + lane : 6 + lane;
         double* __restrict__ stress = (double*)(base + d.off_stress);
         const double* __restrict__ body = d.off_body >= 0 ? (const double*)(base + d.off_body) : nullptr;
         // line profile: each wave adds the sum of u_x over its own columns of
@@ -1071,32 +1113,6 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
             fr.load(rin0, rin1, vm + ro, vc + ro, vp + ro, 0, pbytes);
         };
         auto dens = [&](const R& fr, C& da, C& db) { fr.dens(da, db); };
-        auto halo_fetch = [&](int r) {
-            if (wave == halo_wave(r) && lane < ndma) {
-                const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
-                const int hs = hslot(r);
-                // the slot's LDS base, opaque to the compiler: the destination
-                // of each plane is then one scalar add per load instead of a
-                // value hoisted out of the tick loop (and spilled)
-                __attribute__((address_space(3))) char* hb = (__attribute__((address_space(3))) char*)&hst[hs][0][0];
-                asm volatile("" : "+s"(hb));
-#pragma unroll
-                for (int q = 0; q < 18; ++q) {
-                    const int cx = CX[q % 9];
-                    const unsigned vo = ro + ((!DMA16 && cx > 0) ? vhl : ((!DMA16 && cx < 0) ? vhr : vh));
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)(hb + q * sizeof(hst[0][0])), 4, vo,
-                        __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
-                }
-            }
-        };
-        auto hval = [&](int hs, int q) -> C {
-            if constexpr (DMA16) {
-                return (C)__builtin_bit_cast(S, hst[hs][q][hb16 - CX[q % 9]]);
-            } else {
-                return (C)__builtin_bit_cast(float, hst[hs][q][lane]);
-            }
-        };
         // ring slots: every row index here is >= y0 - 6, so the operands are
         // non-negative and unsigned remainders (cheaper scalar code) are exact
         auto slot6 = [&](int r) { return __builtin_amdgcn_readfirstlane((int)((unsigned)(r - y0 + 8) % 6u)); };
@@ -1107,28 +1123,53 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 c == 0 ? (r & 3) : (c == 1 ? 4 + (int)((unsigned)(r - y0 + 9) % 3u) : 7 + (r & 1)));
         };
 
-        // Step t: stage row r (HBM populations in fr) into ring 0, plus the
-        // four halo entries (lanes 0..3 of the row's halo wave).
+        auto halo_fetch = [&](int r) {
+            if constexpr (HALO) {
+                if (wave == halo_wave(r) && lane < 4) {
+                    const unsigned ro = (unsigned)(map_row<P>(r, ny, walls) * rbytes);
+                    const int hs = hslot(r);
+                    // the slot's LDS base, opaque to the compiler: the destination
+                    // of each plane is then one scalar add per load instead of a
+                    // value hoisted out of the tick loop (and spilled)
+                    __attribute__((address_space(3))) char* hb =
+                        (__attribute__((address_space(3))) char*)&hst[hs][0][0];
+                    asm volatile("" : "+s"(hb));
+#pragma unroll
+                    for (int q = 0; q < 18; ++q) {
+                        const int cx = CX[q % 9];
+                        const unsigned vo = ro + (cx > 0 ? vhl : (cx < 0 ? vhr : vh));
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            q < 9 ? rin0 : rin1, (__attribute__((address_space(3))) void*)(hb + q * sizeof(hst[0][0])),
+                            4, vo, __builtin_amdgcn_readfirstlane((int)((q % 9) * pbytes)), 0, 0);
+                    }
+                }
+            }
+        };
+        // Step t: stage row r (HBM populations in fr) into ring 0, plus (FP32)
+        // the four halo entries (lanes 0..3 of the row's halo wave).
         auto stage1 = [&](const R& fr, int r) {
             const int sp = slot6(r), sr = slot5(r);
             C da, db;
             dens(fr, da, db);
             ringP[0][sp][j + 2] = C2{dpsi<P>(da, e0, inv_rho0), dpsi<P>(db, e1, inv_rho0)};
             ringR[0][sr][j + 2] = C2{da, db};
-            if (wave == halo_wave(r) && lane < 4) {
-                // the row's own loads have completed (da, db); its halo loads
-                // were issued before them, so their data is in LDS
-                asm volatile("" ::"v"(da), "v"(db) : "memory");
-                const int hs = hslot(r);
-                C ha = hval(hs, 0), hb = hval(hs, 9);
+            if constexpr (HALO) {
+                if (wave == halo_wave(r) && lane < 4) {
+                    // the row's own loads have completed (da, db); its halo loads
+                    // were issued before them, so their data is in LDS
+                    asm volatile("" ::"v"(da), "v"(db) : "memory");
+                    const int hs = hslot(r);
+                    auto hval = [&](int q) -> C { return (C)__builtin_bit_cast(float, hst[hs][q][lane]); };
+                    C ha = hval(0), hb = hval(9);
 #pragma unroll
-                for (int q = 1; q < 9; ++q) {
-                    ha += hval(hs, q);
-                    hb += hval(hs, 9 + q);
+                    for (int q = 1; q < 9; ++q) {
+                        ha += hval(q);
+                        hb += hval(9 + q);
+                    }
+                    const int hidx = (lane < 2) ? lane : BW + lane;
+                    ringP[0][sp][hidx] = C2{dpsi<P>(ha, e0, inv_rho0), dpsi<P>(hb, e1, inv_rho0)};
+                    ringR[0][sr][hidx] = C2{ha, hb};
                 }
-                const int hidx = (lane < 2) ? lane : BW + lane;
-                ringP[0][sp][hidx] = C2{dpsi<P>(ha, e0, inv_rho0), dpsi<P>(hb, e1, inv_rho0)};
-                ringR[0][sr][hidx] = C2{ha, hb};
             }
         };
         // Step t+1: row r's populations from the LDS ring, pulled in x (column
@@ -1259,8 +1300,12 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 pair(2, 4, r1, d1, vy);
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
-                auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
-                auto post = [&](int i) -> S { return f.post(o + i, omega, t[i]); };
+                // the stored values and the wall rows' fs, as k_step's
+                S ps[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) ps[i] = f.post(o + i, omega, t[i]);
+                auto fs = [&](int i) -> C { return f[o + i] - omega_w * t[i]; };
+                auto post = [&](int i) -> S { return ps[i]; };
                 if (k == 0) {
                     // into the ring: row y + c_iy at the lane's own index; a
                     // population leaving through a wall returns as OPP[i] at

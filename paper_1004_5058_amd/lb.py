@@ -306,7 +306,7 @@ class Lattice:
 
     def set_fusion(self, steps_per_pass, ly2=0):
         """1 or 2 time steps per pass of the step kernel (2: FP32 or 16-bit
-        population storage; 16-bit needs an even nx)."""
+        population storage)."""
         _check(_lib.lb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def set_fusion_tile(self, lanes):
@@ -458,7 +458,7 @@ class Batch:
 
     def set_fusion(self, steps_per_pass, ly2=0):
         """1 or 2 time steps per pass of the step kernel (2: FP32 or 16-bit
-        population storage; 16-bit needs an even nx in every lattice)."""
+        population storage)."""
         _check(_lib.lbb_set_fusion(self._h, int(steps_per_pass), int(ly2)))
 
     def set_fusion_tile(self, lanes):

@@ -35,6 +35,26 @@ def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_counters("w", "f16x2") is None
 
 
+def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """A comment or layout edit keeps the hash (the counters stay valid for
+    the same code); a change of code does not."""
+    src = tmp_path / "paper_1004_5058_amd" / "csrc"
+    src.mkdir(parents=True)
+    real = os.path.join(ROOT, "paper_1004_5058_amd", "csrc")
+    for name in ("lb_kernels.hip", "lb_device.hpp"):
+        (src / name).write_text(open(os.path.join(real, name), encoding="utf-8").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    k = src / "lb_kernels.hip"
+    text = k.read_text()
+    k.write_text("// a new comment line\n" + text.replace("\n", "\n  ", 3) + "\n/* trailing\n block */\n")
+    assert bench.kernel_source_hash() == h0
+    old = "constexpr int pr_class(int cy) { return cy > 0 ? 0 :"
+    assert old in text
+    k.write_text(text.replace(old, old.replace("? 0 :", "? 1 :"), 1))
+    assert bench.kernel_source_hash() != h0
+
+
 def test_committed_counters_match_the_committed_kernels():
     """profiles/traffic.json is regenerated whenever the step kernel changes."""
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
