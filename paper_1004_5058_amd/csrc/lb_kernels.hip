@@ -1025,7 +1025,9 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     // side instead of loading halo columns, and the edge lanes read ring
     // entries no lane writes (no output depends on them): zero, so that they
     // compute finite values.  The first tick's barrier orders these stores
-    // before any read.
+    // before any read.  Entries: the 22 psi/rho ring rows (ringP 2 x 6, then
+    // ringR 2 x 5) with four each (0, 1, BW + 2, BW + 3), 88 in all, then the
+    // 54 population ring rows (9 x 6) with two each (0, BW + 1).
     if constexpr (!HALO)
     for (int e = tid; e < 22 * 4 + 54 * 2; e += 128 * NW) {
         if (e < 88) {
