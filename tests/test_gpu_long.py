@@ -81,7 +81,7 @@ def test_time_averaged_wall_stress_1024_full_length():
 # is 3e-4 of the largest density (and of the momentum scale).  The averaged
 # stress (~6e-6 here, ~1e-4 of the populations it is made from) and the FP16
 # form are stated under bounds of a few times the measured values (FP32 stress
-# 2e-3, measured 5.3e-4; FP16 5e-2, measured 1.3e-2 fields and 1.4e-2 stress).
+# 2e-3, measured 5.3e-4; FP16 5e-2, measured 1.4e-2 fields and 1.3e-2 stress).
 # BF16 deviation storage does not hold the droplet interfaces over this run
 # (measured: density error 0.24 of the largest density, stress 43 %): the test
 # asserts that it misses the 1 % bar of a flow-curve point (the documented
