@@ -992,7 +992,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     using C = typename P::C;
     using C2 = typename V2<C>::T;
     static_assert(sizeof(S) <= 4, "two fused steps: 4- and 2-byte storage");
-    constexpr bool DMA16 = sizeof(S) == 2;
+    constexpr bool DMA16 = sizeof(S) == 2;   // 2-byte storage: rows packed two per VGPR
     constexpr bool HALO = Fuse2Geom<P>::HALO;
     constexpr int XO = Fuse2Geom<P>::XO;
     constexpr int TW = BW - 2 * XO;
