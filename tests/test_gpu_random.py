@@ -45,8 +45,9 @@ def _draw(seed):
         kw["tau"] = 1.0          # the moment form holds the state at tau = 1 only
     bx = int(r.choice([64, 128, 256] + ([512] if storage in ("f32", "f16dev", "bf16dev") else [])))
     ly = int(r.integers(1, 200))
-    # FP32: two steps per pass in about half of the cases, random fused tile height
-    fuse = storage == "f32" and bool(r.integers(2))
+    # FP32 and 16-bit storage: two steps per pass in about half of the cases,
+    # random fused tile height (16-bit: any nx, odd ones included)
+    fuse = storage in ("f32", "f16dev", "bf16dev") and bool(r.integers(2))
     ly2 = int(r.integers(0, 100))
     return nx, ny, walls, u_top, u_bot, kw, storage, bx, ly, fuse, ly2
 
@@ -112,7 +113,7 @@ def test_random_batch_matches_oracle(seed):
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     grid = int(r.choice([0, ncu, 2 * ncu]))
     graph = int(r.choice([0, 2, 8, 32]))
-    fuse = storage == "f32" and bool(r.integers(2))
+    fuse = storage in ("f32", "f16dev", "bf16dev") and bool(r.integers(2))
     b = lb.Batch(specs, storage=storage, profile=False)
     b.set_launch(bx, ly, grid)
     b.set_graph(graph)
