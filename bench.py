@@ -485,7 +485,7 @@ def main():
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: every GPU box here has one GPU and the library drives one GPU per process; --gpus {a.gpus} "
+        print(f"bench.py: the benchmark runs on one GPU and the library drives one GPU per process; --gpus {a.gpus} "
               "is not supported (sharding by y-slabs with halo rows, or whole lattices per GPU, is designed but not "
               "built).", file=sys.stderr)
         sys.exit(2)
