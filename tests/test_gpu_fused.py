@@ -128,17 +128,21 @@ def test_fused_matches_oracle():
     print(f"\nfused FP32 {nx}x{ny}, {steps} steps: {e}")
 
 
-def test_fused_batch_equals_single_steps():
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+def test_fused_batch_equals_single_steps(storage):
+    """A batch of uneven lattices (odd widths among them), each with its own
+    walls, wall speed, couplings and tau, two steps per pass against one."""
     from paper_1004_5058_amd import lb
     specs = []
-    for k, (nx, ny, walls) in enumerate([(512, 256, True), (300, 77, False), (1024, 130, True), (40, 9, True)]):
+    for k, (nx, ny, walls) in enumerate([(512, 256, True), (301, 77, False), (1024, 130, True), (41, 9, True),
+                                         (7, 33, False)]):
         ra, rb = inputs.emulsion(nx, ny, seed=20 + k)
         u = 0.01 * (k + 1) if walls else 0.0
         specs.append(dict(nx=nx, ny=ny, rho_a=ra, rho_b=rb, ux=None, uy=None, walls=walls, u_top=u, u_bot=-u,
-                          g_aa2=7.8 + 0.1 * k))
+                          g_aa2=7.8 + 0.1 * k, tau=0.8 + 0.15 * k))
     res = []
     for fused in (False, True):
-        b = lb.Batch(specs, storage="f32", profile=False)
+        b = lb.Batch(specs, storage=storage, profile=False)
         if fused:
             b.set_fusion(2)
         b.step(24)
