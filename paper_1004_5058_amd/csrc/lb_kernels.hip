@@ -112,15 +112,6 @@ __device__ __forceinline__ void st_s(rsrc_t r, unsigned voff, unsigned soff, typ
     bstore<typename P::S>(v, r, voff, (unsigned)__builtin_amdgcn_readfirstlane((int)soff));
 }
 
-// A copy of x the compiler cannot see through: an expression written with it
-// is never merged with the same expression written with x.
-template <class T>
-__device__ __forceinline__ T opaque(T x)
-{
-    asm("" : "+v"(x));
-    return x;
-}
-
 // A value of the arithmetic type, rounded to the storage format on its own:
 // the value is first rounded to the arithmetic type, so the compiler cannot
 // fuse the conversion into the multiply-add that produced it (for FP16 that
@@ -144,7 +135,7 @@ __device__ __forceinline__ S to_store(C x)
 // collision needs, in one fixed order (left to right): the species densities
 // (dens), the momentum (mom), the deviation f_q - x of one population from a
 // value (dev), and the post-collision value f_q - w t in the storage format,
-// rounded once (post).
+// rounded from its FP32 value (post).
 template <class P, bool PACK = (sizeof(typename P::S) == 2)> struct Row;
 
 // The sums in the arithmetic type, through the row's operator[].
@@ -195,18 +186,6 @@ __device__ __forceinline__ float mix_pair(unsigned a, unsigned b)
             : "=v"(r) : "v"(b), "v"(a), "n"(HB), "n"(HA));
     return r;
 }
-// The FP16 rounding of h - w t, rounded once (v_fma_mixlo_f16 writes the low
-// half of its destination).
-template <int H>
-__device__ __forceinline__ _Float16 mix_post(unsigned p, float w, float t)
-{
-    unsigned r;
-    if constexpr (H)
-        asm("v_fma_mixlo_f16 %0, -%1, %2, %3 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(w), "v"(t), "v"(p));
-    else
-        asm("v_fma_mixlo_f16 %0, -%1, %2, %3 op_sel:[0,0,0] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(w), "v"(t), "v"(p));
-    return __builtin_bit_cast(_Float16, (unsigned short)r);
-}
 template <int H>
 __device__ __forceinline__ float mix_dev(unsigned p, float x)
 {
@@ -225,7 +204,7 @@ template <class P> struct Row<P, false> {
     __device__ __forceinline__ void dens(C& da, C& db) const { row_dens(*this, da, db); }
     __device__ __forceinline__ void mom(C& jx, C& jy) const { row_mom(*this, jx, jy); }
     __device__ __forceinline__ C dev(int q, C x) const { return v[q] - x; }
-    __device__ __forceinline__ C post(int q, C w, C t) const { return v[q] - w * t; }
+    __device__ __forceinline__ C post(int q, C w, C t) const { return v[q] - w * t; }   // S = C
     // Planes are stored shifted in x by c_ix: population q of the lane's node
     // sits one column left (c_ix = +1: vl), in place (vc) or one column right
     // (c_ix = -1: vr).  so: uniform SGPR byte offset; v*: per-lane byte offsets.
@@ -291,16 +270,13 @@ template <class P> struct Row<P, true> {
             return (*this)[q] - x;
         }
     }
-    // FP16: one v_fma_mixlo_f16 written out (left to the compiler, whether the
-    // conversion fused into the multiply-add depended on the surrounding code)
+    // the FP32 value rounded to the storage format (FP16 through to_store:
+    // the compiler would otherwise fuse the conversion into the multiply-add
+    // at some stores and not at others; BF16 has no such fusion)
     __device__ __forceinline__ S post(int q, float w, float t) const
     {
-        if constexpr (MIX) {
-            const unsigned p = __builtin_bit_cast(unsigned, v[q >> 1]);
-            return (q & 1) ? mix_post<1>(p, w, t) : mix_post<0>(p, w, t);
-        } else {
-            return (S)((*this)[q] - w * t);
-        }
+        if constexpr (MIX) return to_store<S>((*this)[q] - w * t);
+        else return (S)((*this)[q] - w * t);
     }
     __device__ __forceinline__ void load(rsrc_t r0, rsrc_t r1, unsigned vl, unsigned vc, unsigned vr, unsigned so,
                                          unsigned pbytes)
@@ -607,7 +583,6 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
         const unsigned xm = (xc == 0) ? (unsigned)(nx - 1) : xc - 1;
 
         const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
-        const C omega_w = opaque(omega);   // the wall rows' omega (fs below)
         const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
         C ks0[5], ks1[5];
 #pragma unroll
@@ -840,15 +815,12 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
                 if (!valid) return;
-                // the nine stored values, rounded once each (post), before any
-                // wall branch: computed together they schedule better than at
-                // each store (about 1 % of the FP16 two-step kernel); the wall
-                // rows also use the value in the arithmetic type (fs, with a
-                // copy of omega: its multiply-add stays apart from post's)
+                // the nine stored values (post), before any wall branch; the
+                // wall rows also use them in the arithmetic type (fs)
                 S ps[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) ps[i] = f.post(o + i, omega, t[i]);
-                auto fs = [&](int i) -> C { return f[o + i] - omega_w * t[i]; };
+                auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
                 const rsrc_t ro = (s == 0) ? rout0 : rout1;
                 if (!(bot || top)) {
                     // interior row: push to rows y-1, y, y+1 (periodic wrap)
@@ -1065,7 +1037,6 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
         const bool own = j >= XO && j < XO + TW && X + (j - XO) < nx;
 
         const C tau = coef<C>(d.tau, d.ftau), omega = coef<C>(d.omega, d.fomega);
-        const C omega_w = opaque(omega);   // the wall rows' omega (fs below)
         const C inv_rho0 = coef<C>(d.inv_rho0, d.finv_rho0);
         C ks0[5], ks1[5];
 #pragma unroll
@@ -1306,7 +1277,7 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 S ps[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) ps[i] = f.post(o + i, omega, t[i]);
-                auto fs = [&](int i) -> C { return f[o + i] - omega_w * t[i]; };
+                auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
                 auto post = [&](int i) -> S { return ps[i]; };
                 if (k == 0) {
                     // into the ring: row y + c_iy at the lane's own index; a
