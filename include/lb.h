@@ -68,7 +68,10 @@ typedef enum {
  * reference densities, rounded to nearest-even, and the step computes on
  * deviations (density deviations, deviations of psi from psi(rho_ref)), so the
  * rounding error scales with the departure from the reference state rather
- * than with f itself.  Arithmetic is FP64 for LB_F64 and FP32 otherwise.
+ * than with f itself.  Arithmetic is FP64 for LB_F64 and FP32 otherwise; a
+ * step stores each post-collision deviation computed in the arithmetic type
+ * and then rounded to the storage format (one rule for every kernel and launch
+ * shape).
  *
  * LB_MOM32 / LB_MOM64 (FP32 / FP64): the moment form, valid only at tau = 1
  * (lb_params.tau must be exactly 1; anything else is LB_EINVAL).  With tau = 1
