@@ -169,18 +169,19 @@ def test_fused_refused_where_not_built():
         lat.close()
 
 
-def test_autotune_considers_two_steps_per_pass(tmp_path):
-    """The tuner also times two steps per pass for an FP32 lattice, applies
-    the faster mode, preserves the state (either mode is bitwise the
-    single-step result) and records the choice in the cache; a profile-enabled
-    lattice of the same key applies the cached entry and accumulates its
-    profile."""
+@pytest.mark.parametrize("storage,nx", [("f32", 1024), ("f16dev", 1023)])
+def test_autotune_considers_two_steps_per_pass(tmp_path, storage, nx):
+    """The tuner also times two steps per pass for an FP32 or 16-bit lattice
+    (odd nx included), applies the faster mode, preserves the state (either
+    mode is bitwise the single-step result) and records the choice in the
+    cache; a profile-enabled lattice of the same key applies the cached entry
+    and accumulates its profile."""
     import json
-    nx, ny, u = 1024, 512, 0.02
+    ny, u = 512, 0.02
     ra, rb = inputs.emulsion(nx, ny, seed=3)
-    ref = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32")
+    ref = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage)
     ref.step(10)
-    lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32")
+    lat = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage)
     lat.step(4)
     cache = str(tmp_path / "tune.json")
     bx, ly, ms = lat.autotune(cache, steps=4)
@@ -195,7 +196,7 @@ def test_autotune_considers_two_steps_per_pass(tmp_path):
     if ent["ly2"]:
         assert c["ly2"] == ent["ly2"]
     print(f"\n{key}: {ent}")
-    prof = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage="f32", profile=True)
+    prof = gpu_lattice(nx, ny, ra, rb, u_top=u, u_bot=-u, storage=storage, profile=True)
     assert prof.autotune(cache, steps=4)[:2] == (bx, ly)
     prof.step(4)
     assert prof.time() == 4 and prof.profile()[1] == 4
