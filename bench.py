@@ -28,9 +28,10 @@ length and the record of the 5000-step workload length.  `cpu_baseline` is
 the FP64 oracle on all host threads, with a single-thread rate beside it.
 
 Before each variant's warm-up, the same step kernel runs for half a second on
-a separate lattice of the same size and storage (clock ramp), the warm-up
-steps queued right behind it: the first tens of launches after even a few
-tens of milliseconds of idle GPU run 10-20 % slow.
+a separate lattice of the same size, storage and initial state (clock ramp),
+the warm-up steps queued right behind it: the first tens of launches after
+even a few tens of milliseconds of idle GPU run 10-20 % slow, and a ramp on
+other data (uniform densities) left the 16-bit forms' first launches slow.
 
 The launch shape comes from the project's autotuner (timed before the timed
 region; cached in paper_1004_5058_amd/tuning.json).  A second leg measures
@@ -177,17 +178,6 @@ def run_ramp(lat, seconds, then=None):
         then()
     torch.cuda.synchronize()
     return done
-
-
-def clock_ramp(variant, n, seconds, tune_cache=None, u=0.02):
-    """Runs the variant's step kernel for `seconds` on a separate lattice and
-    discards it (for work that follows at once).  Returns the steps taken."""
-    lat = ramp_lattice(variant, n, tune_cache=tune_cache, u=u)
-    try:
-        return run_ramp(lat, seconds)
-    finally:
-        lat.close()
-        del lat
 
 
 def gpu_run(variant, n, steps, warmup, u=0.02, seed=1, tune_cache=None, ramp_s=0.0):
@@ -553,6 +543,7 @@ def main():
                      "valu_busy": (measured_counters(workload, head) or {}).get("valu_busy")},
         "variants": {},
         "clock_ramp": (f"{a.ramp:g} s of the same step kernel on a separate {n}x{n} lattice of the same storage "
+                       "and initial state "
                        f"({r['ramp_steps']} steps), the {a.warmup} warm-up steps queued right behind it") if a.ramp > 0
         else None,
     }
