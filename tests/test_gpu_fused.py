@@ -86,6 +86,18 @@ def test_fused_odd_steps_and_graph_parity(steps, graph, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("nx", [1, 2, 3, 5])
+@pytest.mark.parametrize("walls", [True, False])
+def test_fused_tiny_widths(storage, nx, walls):
+    """Lattices narrower than the stencil: every lane of a tile wraps onto a
+    few columns (one column: all lanes hold the same site)."""
+    (p1, s1, t1), (p2, s2, t2) = _pair(nx, 7, storage, walls, not walls, 13, 0, 0, init="noise")
+    assert t1 == t2 == 13
+    np.testing.assert_array_equal(p2, p1)
+    assert s2 == s1
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
 @pytest.mark.parametrize("lanes", [128, 192, 256])
 def test_fused_odd_width(lanes, storage):
     """Odd nx: the tiles' columns wrap around the periodic x at an odd
