@@ -197,9 +197,10 @@ lb_status lb_set_fusion(lb_handle* h, int32_t steps_per_pass, int32_t ly2);
 /* Block width of the two-steps-per-pass kernel: lanes = 128, 192 or 256
  * threads per time step (the block has twice as many), or 0 for the width
  * with the most waves resident per compute unit.  A tile stores lanes - 6
- * columns (FP32) or lanes - 10 (16-bit): the step-t columns beyond them are
- * the overlap step t+1 needs (16-bit: also the two columns each side whose
- * densities step t's stencil needs, where FP32 loads them as halo columns).
+ * columns (FP32 at 128 lanes) or lanes - 10 (the other widths and the 16-bit
+ * forms): the step-t columns beyond them are the overlap step t+1 needs (for
+ * lanes - 10 also the two columns each side whose densities step t's stencil
+ * needs, which FP32 at 128 lanes loads as halo columns).
  * Results are bitwise independent of the width.
  * LB_EINVAL for another value. */
 lb_status lb_set_fusion_tile(lb_handle* h, int32_t lanes);

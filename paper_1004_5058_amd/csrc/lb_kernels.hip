@@ -925,14 +925,17 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
 // so the pair of steps is bitwise that of two k_step launches; each
 // population crosses HBM once per two updates.
 //
-// Column offset XO.  FP32: 3 (TW = BW - 6); step t's stencil reads the two
-// columns beyond each side of its lanes as halo columns (direct-to-LDS loads
-// by one wave per row, as in k_step).  16-bit: 5 (TW = BW - 10); the tile
-// overlaps its neighbours by two more columns each side instead, so every
-// wave does the same work per tick (no halo wave for the others to wait for
-// at the barrier): about 3 % (FP16) and 4 % (BF16) faster per step at 4096^2
-// than the halo form, which for FP32 with its narrower 128-lane tiles was 6 %
-// slower.  The edge lanes' results feed no output.
+// Column offset XO.  FP32 at 128 lanes per step: 3 (TW = BW - 6); step t's
+// stencil reads the two columns beyond each side of its lanes as halo columns
+// (direct-to-LDS loads by one wave per row, as in k_step).  The 16-bit forms
+// and FP32 at 192 or 256 lanes: 5 (TW = BW - 10); the tile overlaps its
+// neighbours by two more columns each side instead, so every wave does the
+// same work per tick (no halo wave for the others to wait for at the
+// barrier).  At 4096^2 the overlap form ran FP16 about 3 % and BF16 4 %
+// faster per step than the halo form, and FP32 at 256 lanes 6 % faster (then
+// 1 % faster than the 128-lane halo form); at 128 lanes, where the two more
+// columns cost 3 % of the tile, FP32 ran 7 % slower with it.  The edge lanes'
+// results feed no output.
 //
 // The population ring is split by the y direction of the population, since
 // each class lives for a different number of ticks (rows r written at
@@ -945,9 +948,10 @@ k_step(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* __
 // Nine rows of six planes instead of four rows of eighteen; with the
 // five-row rho ring (the rho stencil is belt 1 only) three blocks of 128
 // FP32 lanes per step fit in a CU's 160 KiB of LDS.
-template <class P> struct Fuse2Geom {
-    // FP32: halo columns by direct-to-LDS loads; 16-bit: overlapping tiles
-    static constexpr bool HALO = sizeof(typename P::S) == 4;
+template <class P, int NW> struct Fuse2Geom {
+    // FP32 at two waves per step: halo columns by direct-to-LDS loads; the
+    // other widths and the 16-bit forms: overlapping tiles
+    static constexpr bool HALO = sizeof(typename P::S) == 4 && NW == 2;
     static constexpr int XO = HALO ? 3 : 5;
 };
 constexpr int pr_class(int cy) { return cy > 0 ? 0 : (cy == 0 ? 1 : 2); }
@@ -965,8 +969,8 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
     using C2 = typename V2<C>::T;
     static_assert(sizeof(S) <= 4, "two fused steps: 4- and 2-byte storage");
     constexpr bool DMA16 = sizeof(S) == 2;   // 2-byte storage: rows packed two per VGPR
-    constexpr bool HALO = Fuse2Geom<P>::HALO;
-    constexpr int XO = Fuse2Geom<P>::XO;
+    constexpr bool HALO = Fuse2Geom<P, NW>::HALO;
+    constexpr int XO = Fuse2Geom<P, NW>::XO;
     constexpr int TW = BW - 2 * XO;
     // psi rings [step][slot][column index j + 2] (six rows), rho rings (five
     // rows); indices 0, 1, BW + 2 and BW + 3 are step t's halo columns (FP32)

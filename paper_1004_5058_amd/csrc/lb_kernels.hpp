@@ -16,8 +16,10 @@ hipError_t launch_step(int storage, int bx, char* base, const LatDesc* descs, co
 // src ^ 1.  FP32 and 16-bit storage (codes 1, 2, 3); nw = 2, 3 or 4 waves per
 // step, blocks of 128 nw threads, tiles of fuse2_tw(storage, nw) output
 // columns (the step t+1 columns of a 64 nw lane strip less the overlap).
-constexpr int fuse2_xo(int storage) { return (storage == 2 || storage == 3) ? 5 : 3; }
-constexpr int fuse2_tw(int storage, int nw) { return 64 * nw - 2 * fuse2_xo(storage); }
+// Column offset: FP32 at two waves per step loads halo columns (3); the
+// other forms overlap their tiles by two more columns instead (5).
+constexpr int fuse2_xo(int storage, int nw) { return (storage == 1 && nw == 2) ? 3 : 5; }
+constexpr int fuse2_tw(int storage, int nw) { return 64 * nw - 2 * fuse2_xo(storage, nw); }
 constexpr int FUSE2_NW_MIN = 2, FUSE2_NW_MAX = 4;
 hipError_t launch_step2(int storage, int nw, char* base, const LatDesc* descs, const int* tiles, int ntot, int src,
                         int grid, hipStream_t s);
