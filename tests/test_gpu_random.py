@@ -60,13 +60,17 @@ def test_random_configuration_matches_oracle(seed):
     g, _, _ = oracle_run(p, ra, rb, None, None, 30)
     lat = gpu_lattice(nx, ny, ra, rb, walls=walls, u_top=u_top, u_bot=u_bot, storage=storage, **kw)
     lat.set_launch(bx, ly)
+    # the fused block width from a generator of its own (the draws above
+    # stay those of earlier sweeps): 128, 192 or 256 lanes or automatic
+    lanes = int(np.random.default_rng(9000 + seed).choice([0, 128, 192, 256]))
     if fuse:
+        lat.set_fusion_tile(lanes)
         lat.set_fusion(2, ly2)
     lat.step(30)
     tol = TOL[storage]
     e = compare_fields(lat, p, g, tol)
     ep = err_pop(lat.populations(), g)
-    print(f"\nseed {seed}: {nx}x{ny} walls={walls} {storage}{' fused ly2 %d' % ly2 if fuse else ''} "
+    print(f"\nseed {seed}: {nx}x{ny} walls={walls} {storage}{' fused ly2 %d lanes %d' % (ly2, lanes) if fuse else ''} "
           f"shape {bx}x{ly} tau {kw['tau']:.3f}: "
           f"{max(e.values()):.2e}, populations {ep:.2e}")
     assert ep <= 10 * tol
@@ -117,7 +121,9 @@ def test_random_batch_matches_oracle(seed):
     b = lb.Batch(specs, storage=storage, profile=False)
     b.set_launch(bx, ly, grid)
     b.set_graph(graph)
+    lanes = int(np.random.default_rng(9500 + seed).choice([0, 128, 192, 256]))
     if fuse:
+        b.set_fusion_tile(lanes)
         b.set_fusion(2, int(r.integers(0, 60)))
     b.step(30)
     worst = 0.0
@@ -126,6 +132,6 @@ def test_random_batch_matches_oracle(seed):
         e = compare_fields(_Member(b, k), p, g, TOL[storage])
         worst = max(worst, max(e.values()))
     b.close()
-    print(f"\nbatch seed {seed}: {len(specs)} lattices {storage}{' fused' if fuse else ''} shape {bx}x{ly} "
+    print(f"\nbatch seed {seed}: {len(specs)} lattices {storage}{' fused lanes %d' % lanes if fuse else ''} shape {bx}x{ly} "
           f"grid {grid} graph {graph}: "
           f"worst {worst:.2e}")
