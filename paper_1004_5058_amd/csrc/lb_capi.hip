@@ -611,24 +611,27 @@ lb_status batch_init(const lb_params* params, int32_t n, void* dev_state, size_t
     if (((uintptr_t)dev_state) % ALIGN) return fail(LB_EINVAL, "device state must be 256-byte aligned");
     if (!ra || !rb) return fail(LB_EINVAL, "null initial density arrays");
     std::vector<Lat> lats(n);
+    std::vector<size_t> nsites(n);
     for (int k = 0; k < n; ++k) {
         lb_status st = validate(&params[k], params[0].storage);
         if (st != LB_OK) return st;
         lats[k].p = params[k];
         if (!ra[k] || !rb[k]) return fail(LB_EINVAL, "null initial density of lattice %d", k);
-        const size_t ns = (size_t)params[k].nx * params[k].ny;
-        double sum[2] = {0, 0};
-        for (size_t i = 0; i < ns; ++i) {
-            const double a = ra[k][i], b = rb[k][i];
-            if (!(a > 0.0) || !(b > 0.0) || !std::isfinite(a) || !std::isfinite(b))
-                return fail(LB_EINVAL, "lattice %d: initial density must be finite and > 0 (site %zu)", k, i);
-            sum[0] += a;
-            sum[1] += b;
-            if (ux && ux[k] && !std::isfinite(ux[k][i])) return fail(LB_EINVAL, "non-finite initial ux");
-            if (uy && uy[k] && !std::isfinite(uy[k][i])) return fail(LB_EINVAL, "non-finite initial uy");
-        }
-        lats[k].rho_ref[0] = params[k].rho_ref_a > 0 ? params[k].rho_ref_a : sum[0] / ns;
-        lats[k].rho_ref[1] = params[k].rho_ref_b > 0 ? params[k].rho_ref_b : sum[1] / ns;
+        nsites[k] = (size_t)params[k].nx * params[k].ny;
+    }
+    // the fields of all lattices checked and summed on the host threads (each
+    // lattice's sums in site order, whatever the thread count)
+    std::vector<lbh::FieldCheck> chk(n);
+    lbh::check_fields(n, nsites.data(), ra, rb, ux, uy, chk.data(), 0);
+    for (int k = 0; k < n; ++k) {
+        const lbh::FieldCheck& c = chk[k];
+        if (c.what == 1)
+            return fail(LB_EINVAL, "lattice %d: initial density must be finite and > 0 (site %zu)", k, c.site);
+        if (c.what == 2) return fail(LB_EINVAL, "lattice %d: non-finite initial ux (site %zu)", k, c.site);
+        if (c.what == 3) return fail(LB_EINVAL, "lattice %d: non-finite initial uy (site %zu)", k, c.site);
+        const double ns = (double)nsites[k];
+        lats[k].rho_ref[0] = params[k].rho_ref_a > 0 ? params[k].rho_ref_a : c.sum[0] / ns;
+        lats[k].rho_ref[1] = params[k].rho_ref_b > 0 ? params[k].rho_ref_b : c.sum[1] / ns;
     }
     Layout lay = plan(lats);
     if (bytes < lay.total)

@@ -8,6 +8,10 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <algorithm>
+#include <atomic>
+#include <thread>
+
 namespace lbh {
 
 size_t storage_size(int storage)
@@ -132,6 +136,55 @@ bool parse_line(const std::string& line, std::pair<std::string, TuneEntry>* out)
 }
 
 }  // namespace
+
+namespace {
+
+void check_one(size_t ns, const double* ra, const double* rb, const double* ux, const double* uy, FieldCheck* c)
+{
+    double s0 = 0, s1 = 0;
+    for (size_t i = 0; i < ns; ++i) {
+        const double a = ra[i], b = rb[i];
+        if (!(a > 0.0) || !(b > 0.0) || !std::isfinite(a) || !std::isfinite(b)) { c->what = 1; c->site = i; return; }
+        s0 += a;
+        s1 += b;
+        if (ux && !std::isfinite(ux[i])) { c->what = 2; c->site = i; return; }
+        if (uy && !std::isfinite(uy[i])) { c->what = 3; c->site = i; return; }
+    }
+    c->sum[0] = s0;
+    c->sum[1] = s1;
+}
+
+}  // namespace
+
+void check_fields(int n, const size_t* ns, const double* const* ra, const double* const* rb,
+                  const double* const* ux, const double* const* uy, FieldCheck* out, int threads)
+{
+    if (n < 1) return;
+    for (int k = 0; k < n; ++k) out[k] = FieldCheck();
+    // the largest lattices first, so that the last one a thread takes is short
+    std::vector<int> order(n);
+    for (int k = 0; k < n; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ns[a] > ns[b]; });
+    std::atomic<int> next(0);
+    auto work = [&]() {
+        for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) {
+            const int k = order[i];
+            check_one(ns[k], ra[k], rb[k], ux ? ux[k] : nullptr, uy ? uy[k] : nullptr, &out[k]);
+        }
+    };
+    if (threads <= 0) threads = std::min(16, (int)std::max(1u, std::thread::hardware_concurrency()));
+    threads = std::min(threads, n);
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (...) {
+            break;   // fewer threads: the calling thread takes the rest
+        }
+    }
+    work();
+    for (std::thread& t : pool) t.join();
+}
 
 TuneCache parse_cache(const char* text, size_t len)
 {

@@ -50,6 +50,21 @@ inline int fused_nseg(int ny, int ly2)
 // the reason in *msg.
 lb_status validate(const lb_params* p, int storage0, std::string* msg);
 
+// One lattice's initial fields, checked.
+struct FieldCheck {
+    int what = 0;             // 0: valid; 1: a density not finite and > 0; 2: a non-finite u_x; 3: a non-finite u_y
+    size_t site = 0;          // the first offending site (row-major), where what != 0
+    double sum[2] = {0, 0};   // sums of rho_A and of rho_B over the sites, in site order
+};
+// Checks the initial fields of n lattices (ns[k] sites each; ux, uy and any of
+// their entries may be null) and sums each lattice's densities in site order,
+// one sequential pass per lattice that stops at its first offending site (at a
+// site: the densities, then u_x, then u_y).  The lattices are spread over up
+// to `threads` host threads (<= 0: the hardware's, at most 16), the largest
+// first; the results do not depend on the thread count.
+void check_fields(int n, const size_t* ns, const double* const* ra, const double* const* rb,
+                  const double* const* ux, const double* const* uy, FieldCheck* out, int threads);
+
 // One autotuner result.
 struct TuneEntry {
     int bx = 0, ly = 0, grid = 0;

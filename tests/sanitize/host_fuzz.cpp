@@ -1,6 +1,6 @@
 // Sanitizer harness of the library's host-only logic (csrc/lb_host.cpp):
-// parameter validation, the tuning-cache parser and the checkpoint header
-// checks, fed valid and malformed inputs.  Built with
+// parameter validation, the initial-field checks, the tuning-cache parser and
+// the checkpoint header checks, fed valid and malformed inputs.  Built with
 // -fsanitize=address,undefined by tests/test_host_sanitize.py; any invalid
 // memory access, leak or undefined behaviour aborts it, and every expected
 // result is checked here.
@@ -202,10 +202,77 @@ static void test_fused_segments()
     EXPECT(lbh::fused_nseg(16, 16) == 2 && lbh::fused_nseg(16, 8) == 2);
 }
 
+// Initial-field checks of several lattices over 1..16 threads: the same sums,
+// bit for bit, as one sequential pass per lattice, and the first offending
+// site of each kind.
+static void test_fields()
+{
+    std::mt19937_64 rng(7);
+    std::uniform_real_distribution<double> U(0.05, 1.5);
+    const size_t sizes[] = {1, 2, 3, 64, 1000, 4097, 20000, 7, 512, 999};
+    const int n = (int)(sizeof sizes / sizeof sizes[0]);
+    std::vector<std::vector<double>> a(n), b(n), u(n), v(n);
+    std::vector<const double*> pa(n), pb(n), pu(n), pv(n);
+    std::vector<double> ref0(n), ref1(n);
+    for (int k = 0; k < n; ++k) {
+        for (size_t i = 0; i < sizes[k]; ++i) {
+            a[k].push_back(U(rng));
+            b[k].push_back(U(rng));
+            u[k].push_back(U(rng) - 0.5);
+            v[k].push_back(U(rng) - 0.5);
+        }
+        double s0 = 0, s1 = 0;
+        for (size_t i = 0; i < sizes[k]; ++i) {
+            s0 += a[k][i];
+            s1 += b[k][i];
+        }
+        ref0[k] = s0;
+        ref1[k] = s1;
+        pa[k] = a[k].data();
+        pb[k] = b[k].data();
+        pu[k] = u[k].data();
+        pv[k] = (k % 3 == 1) ? nullptr : v[k].data();   // some lattices without u_y
+    }
+    for (int threads : {1, 2, 3, 16, 0}) {
+        std::vector<lbh::FieldCheck> c(n);
+        lbh::check_fields(n, sizes, pa.data(), pb.data(), pu.data(), pv.data(), c.data(), threads);
+        for (int k = 0; k < n; ++k)
+            EXPECT(c[k].what == 0 && c[k].sum[0] == ref0[k] && c[k].sum[1] == ref1[k]);
+        lbh::check_fields(n, sizes, pa.data(), pb.data(), nullptr, nullptr, c.data(), threads);
+        for (int k = 0; k < n; ++k) EXPECT(c[k].what == 0 && c[k].sum[0] == ref0[k]);
+    }
+    // planted faults: the first one in site order is reported, densities
+    // before u_x before u_y at one site
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const double inf = std::numeric_limits<double>::infinity();
+    a[4][700] = -0.0;
+    u[4][300] = inf;
+    b[5][10] = nan;
+    u[6][5000] = nan;
+    v[6][5000] = nan;
+    v[9][998] = -inf;
+    a[3][63] = 0.0;
+    u[0][0] = nan;
+    for (int threads : {1, 4, 0}) {
+        std::vector<lbh::FieldCheck> c(n);
+        lbh::check_fields(n, sizes, pa.data(), pb.data(), pu.data(), pv.data(), c.data(), threads);
+        EXPECT(c[0].what == 2 && c[0].site == 0);
+        EXPECT(c[1].what == 0 && c[2].what == 0 && c[7].what == 0 && c[8].what == 0);
+        EXPECT(c[3].what == 1 && c[3].site == 63);
+        EXPECT(c[4].what == 2 && c[4].site == 300);
+        EXPECT(c[5].what == 1 && c[5].site == 10);
+        EXPECT(c[6].what == 2 && c[6].site == 5000);
+        EXPECT(c[9].what == 3 && c[9].site == 998);
+        EXPECT(c[1].sum[0] == ref0[1] && c[8].sum[1] == ref1[8]);
+    }
+    lbh::check_fields(0, sizes, pa.data(), pb.data(), nullptr, nullptr, nullptr, 4);   // nothing to do
+}
+
 int main()
 {
     test_fused_segments();
     test_validate();
+    test_fields();
     test_cache();
     test_checkpoint();
     if (failures) {

@@ -123,6 +123,50 @@ def test_init_rejects_bad_inputs_before_device_work():
     assert L.lb_step(None, 1) == -1
 
 
+def test_batch_init_names_the_lattice_and_site_of_a_bad_field():
+    """A batch's initial fields are checked on several host threads; the error
+    names the lowest-numbered lattice at fault and its first offending site
+    (densities before u_x before u_y), and nothing touches a GPU."""
+    from paper_1004_5058_amd import lb
+    L = lb.load_library()
+    shapes = [(8, 8), (16, 12), (40, 24), (12, 10)]
+    P = (lb.lb_params * len(shapes))()
+    for k, (nx, ny) in enumerate(shapes):
+        P[k] = lb.make_params(nx, ny)
+    need = ctypes.c_size_t()
+    assert L.lbb_state_bytes(P, len(shapes), ctypes.byref(need)) == 0
+    fields = {key: [np.full((ny, nx), 0.5 if key.startswith("rho") else 0.01) for nx, ny in shapes]
+              for key in ("rho_a", "rho_b", "ux", "uy")}
+
+    def init():
+        ptrs = {}
+        for key, arrs in fields.items():
+            ptrs[key] = (lb._DP * len(shapes))(*[lb._dptr(a) for a in arrs])
+        h = ctypes.c_void_p()
+        rc = L.lbb_init(P, len(shapes), ctypes.c_void_p(4096), 0, None, ptrs["rho_a"], ptrs["rho_b"],
+                        ptrs["ux"], ptrs["uy"], ctypes.byref(h))
+        return rc, L.lb_last_error().decode()
+
+    # valid fields: the device-state size check is the first failure
+    rc, msg = init()
+    assert rc == -2 and "smaller" in msg
+    fields["uy"][3][2, 5] = float("inf")
+    fields["ux"][2][7, 3] = float("nan")
+    fields["rho_b"][2][9, 1] = 0.0
+    rc, msg = init()
+    assert rc == -1 and "lattice 2" in msg and "non-finite initial ux" in msg and f"site {7 * 40 + 3}" in msg
+    fields["rho_a"][2][0, 39] = -1.0
+    rc, msg = init()
+    assert rc == -1 and "lattice 2" in msg and "density" in msg and "site 39" in msg
+    fields["rho_a"][2][0, 39] = 0.5
+    fields["ux"][2][7, 3] = 0.0
+    rc, msg = init()
+    assert rc == -1 and "lattice 2" in msg and "density" in msg and f"site {9 * 40 + 1}" in msg
+    fields["rho_b"][2][9, 1] = 0.5
+    rc, msg = init()
+    assert rc == -1 and "lattice 3" in msg and "non-finite initial uy" in msg and f"site {2 * 12 + 5}" in msg
+
+
 def test_moment_storage_requires_tau_one():
     """The moment form holds the post-collision state only at tau = 1."""
     from paper_1004_5058_amd import lb
