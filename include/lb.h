@@ -264,6 +264,10 @@ const char* lb_last_error(void);
  * advanced together by one persistent step kernel per time step (HIP graph
  * of many steps).  All lattices share the storage precision of params[0].
  * Arrays of per-lattice host pointers follow the single-lattice rules.
+ * lbb_init checks the lattices' initial fields on up to 16 host threads, one
+ * lattice at a time each (the threads end before it returns); a bad field
+ * fails with LB_EINVAL naming the lowest-numbered lattice at fault and its
+ * first offending site, before any device work.
  */
 lb_status lbb_state_bytes(const lb_params* params, int32_t n, size_t* bytes);
 lb_status lbb_init(const lb_params* params, int32_t n, void* dev_state, size_t bytes,
