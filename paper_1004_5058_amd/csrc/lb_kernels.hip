@@ -128,6 +128,28 @@ __device__ __forceinline__ S to_store(C x)
     }
 }
 
+// Two values of the arithmetic type rounded to the storage format on their own
+// (FP16 as to_store, BF16 as the plain conversion).  16-bit storage from FP32:
+// one packed conversion, which rounds each half as the single conversion does.
+template <class S, class C>
+__device__ __forceinline__ void to_store2(C a, C b, S& sa, S& sb)
+{
+    if constexpr (sizeof(S) == 2 && std::is_same<C, float>::value) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef S s2 __attribute__((ext_vector_type(2)));
+        if constexpr (std::is_same<S, _Float16>::value) {
+            asm("" : "+v"(a));
+            asm("" : "+v"(b));
+        }
+        const s2 h = __builtin_convertvector((f2){a, b}, s2);
+        sa = h.x;
+        sb = h.y;
+    } else {
+        sa = to_store<S>(a);
+        sb = to_store<S>(b);
+    }
+}
+
 // The 18 populations of one site held in registers between the row load and
 // the collision: the arithmetic type for 32/64-bit storage; for 16-bit storage
 // the raw values, two per VGPR (d16 loads fill the low and high halves), and
@@ -1278,10 +1300,18 @@ k_step2(char* __restrict__ base, const LatDesc* __restrict__ descs, const int* _
                 pair(5, 7, r2, d2, vx + vy);
                 pair(6, 8, r2, d2, vy - vx);
                 // the stored values and the wall rows' fs, as k_step's
-                S ps[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) ps[i] = f.post(o + i, omega, t[i]);
                 auto fs = [&](int i) -> C { return f[o + i] - omega * t[i]; };
+                S ps[9];
+                if (sizeof(S) == 2 && k == 0) {
+                    // step t's values go to LDS, where the high half of a
+                    // packed pair has its own store
+#pragma unroll
+                    for (int i = 0; i < 8; i += 2) to_store2<S>(fs(i), fs(i + 1), ps[i], ps[i + 1]);
+                    ps[8] = f.post(o + 8, omega, t[8]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) ps[i] = f.post(o + i, omega, t[i]);
+                }
                 auto post = [&](int i) -> S { return ps[i]; };
                 if (k == 0) {
                     // into the ring: row y + c_iy at the lane's own index; a
