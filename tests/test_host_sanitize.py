@@ -44,7 +44,9 @@ def test_host_logic_under_tsan(tmp_path):
     assert r.returncode == 0, r.stderr[-3000:]
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
-    if "unexpected memory mapping" in r.stderr:
-        pytest.skip("ThreadSanitizer cannot map its shadow memory on this kernel")
+    if "FATAL: ThreadSanitizer" in r.stderr:
+        # the runtime could not start here (its shadow memory layout); a race
+        # found is reported as a WARNING and fails below
+        pytest.skip("ThreadSanitizer's runtime cannot start on this host: " + r.stderr.strip()[-200:])
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert "all checks passed" in r.stdout
